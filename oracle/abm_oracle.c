@@ -1,0 +1,498 @@
+/*
+ * abm_oracle.c -- plain, slow, single-threaded CPU oracle for the ABMax
+ * select/update hot path and the predation model built on it.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call this code:
+ * only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.  It shares no source, header, table or helper with the
+ * HIP library; the two are written independently from the paper (arXiv
+ * 2508.16508) and from the fixed model readings stated below.
+ *
+ * Everything here is integer: uint8 masks, int32 state, uint32 hashes and
+ * uint64 conflict keys, so the GPU path must agree bit for bit.
+ *
+ * Structure:
+ *   1. counter-based RNG (SplitMix64 output function, Steele/Lea/Flood 2014)
+ *   2. the paper's toy task, two literal formulations (Sec. 4, Alg. 1 "Rank-
+ *      Match" and Alg. 2 "Sort-Count-Iterate") -- used only to pin (3)
+ *   3. primitives as plain definitions (Sec. 4 toy task; Sec. 2 API list)
+ *   4. the predation model (Sec. 5.1, Fig. 2) step by step in the fixed order
+ *      move, eat, breed, die, regrow
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_API __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------- */
+/* 1. RNG                                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* SplitMix64 output function applied to the state z: add the golden gamma,
+ * then two xor-shift-multiply rounds and a final xor-shift ("Mix13" constants).
+ * mix64(0) is the first SplitMix64 output from seed 0. */
+ORC_API uint64_t orc_mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Counter-based draw keyed on (seed, step, agent, purpose): the high 32 bits
+ * of mix64(mix64(seed:step) xor (agent:purpose)).  No state is carried, so a
+ * run can be resumed from (seed, step) alone. */
+ORC_API uint32_t orc_rng(uint32_t seed, uint32_t step, uint32_t agent, uint32_t purpose)
+{
+    uint64_t inner = orc_mix64(((uint64_t)seed << 32) | (uint64_t)step);
+    uint64_t outer = orc_mix64(inner ^ (((uint64_t)agent << 32) | (uint64_t)purpose));
+    return (uint32_t)(outer >> 32);
+}
+
+/* Lemire multiply-shift reduction of a 32-bit draw onto [0, n). */
+ORC_API uint32_t orc_uniform(uint32_t h, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)h * (uint64_t)n) >> 32);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 2. Toy task of Sec. 4: set the first r = min(p, q) even entries of a to    */
+/*    the first r odd entries of b.                                           */
+/* ------------------------------------------------------------------------- */
+
+static int is_even(int64_t v) { return (v % 2) == 0; }
+static int is_odd(int64_t v) { return (v % 2) != 0; }
+
+/* Rank-Match (Sec. 4, Alg. 1).  Labels are the inclusive cumulative sum of the
+ * mask multiplied by the mask (1-based for selected entries, 0 otherwise).
+ * Every (a_i, b_j) pair yields a candidate: b_j when the labels agree, else
+ * a_i, with an update flag; argmax over the flags (first maximum; 0 when all
+ * flags are false) picks the candidate.  With guard != 0 the labels must also
+ * be positive: without it an unselected a_i (label 0) matches an unselected
+ * b_j (label 0) and is overwritten, which the toy task does not allow. */
+ORC_API void orc_toy_rank_match(const int64_t* a, int64_t n, const int64_t* b, int64_t m,
+                                int guard, int64_t* out)
+{
+    int64_t* ra = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t* rb = (int64_t*)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    int64_t* cand = (int64_t*)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+    uint8_t* mu = (uint8_t*)calloc((size_t)(m > 0 ? m : 1), 1);
+    int64_t cs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ma = is_even(a[i]);
+        cs += ma;
+        ra[i] = cs * ma;
+    }
+    cs = 0;
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t mb = is_odd(b[j]);
+        cs += mb;
+        rb[j] = cs * mb;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (m == 0) { out[i] = a[i]; continue; }
+        for (int64_t j = 0; j < m; ++j) {
+            int match = (ra[i] == rb[j]) && (!guard || ra[i] > 0);
+            cand[j] = match ? b[j] : a[i];
+            mu[j] = (uint8_t)match;
+        }
+        int64_t best = 0; /* argmax: index of the first maximum */
+        for (int64_t j = 1; j < m; ++j)
+            if (mu[j] > mu[best]) best = j;
+        out[i] = cand[best];
+    }
+    free(ra); free(rb); free(cand); free(mu);
+}
+
+/* Sort-Count-Iterate (Sec. 4, Alg. 2).  r = min(#even a, #odd b); a stable
+ * ordering that puts the indices of true mask entries first; then a serial
+ * loop copies b[ib[k]] into a[ia[k]] for k < r. */
+ORC_API void orc_toy_sort_count_iterate(const int64_t* a, int64_t n, const int64_t* b, int64_t m,
+                                        int64_t* out)
+{
+    int64_t* ia = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* ib = (int64_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int64_t p = 0, q = 0, k = 0;
+    for (int64_t i = 0; i < n; ++i) { out[i] = a[i]; p += is_even(a[i]); }
+    for (int64_t j = 0; j < m; ++j) q += is_odd(b[j]);
+    /* stable "trues first" ordering, written as two passes */
+    for (int64_t i = 0; i < n; ++i) if (is_even(a[i])) ia[k++] = i;
+    for (int64_t i = 0; i < n; ++i) if (!is_even(a[i])) ia[k++] = i;
+    k = 0;
+    for (int64_t j = 0; j < m; ++j) if (is_odd(b[j])) ib[k++] = j;
+    for (int64_t j = 0; j < m; ++j) if (!is_odd(b[j])) ib[k++] = j;
+    int64_t r = p < q ? p : q;
+    for (int64_t s = 0; s < r; ++s) out[ia[s]] = b[ib[s]];
+    free(ia); free(ib);
+}
+
+/* ------------------------------------------------------------------------- */
+/* 3. Primitives (plain definitions).  Masks: a byte is "selected" when it is  */
+/*    non-zero.  alive: a slot is live when its value is non-zero.            */
+/* ------------------------------------------------------------------------- */
+
+/* select_agents (Sec. 2): the ascending list of selected indices and its
+ * length.  out_idx may be NULL to count only. */
+ORC_API int64_t orc_select_indices(const uint8_t* mask, int64_t n, int64_t* out_idx)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (mask[i]) {
+            if (out_idx) out_idx[k] = i;
+            ++k;
+        }
+    }
+    return k;
+}
+
+/* Distinct updates to a dynamically selected subset (Sec. 4 toy task).
+ * p = #selected slots, q = #selected records (all n_rec records when
+ * upd_mask is NULL), r = min(p, q).  The j-th selected slot (ascending) takes
+ * every attribute of the j-th selected record (ascending), for j < r.
+ * Nothing else changes.  applied = r, dropped = q - r. */
+ORC_API void orc_select_update(int64_t n, int32_t n_attrs, int32_t* const* attr,
+                               const uint8_t* sel_mask, int64_t n_rec,
+                               const int32_t* const* rec, const uint8_t* upd_mask,
+                               int64_t* applied, int64_t* dropped)
+{
+    int64_t* A = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* B = (int64_t*)malloc((size_t)(n_rec > 0 ? n_rec : 1) * sizeof(int64_t));
+    int64_t p = orc_select_indices(sel_mask, n, A);
+    int64_t q;
+    if (upd_mask) {
+        q = orc_select_indices(upd_mask, n_rec, B);
+    } else {
+        q = n_rec;
+        for (int64_t j = 0; j < n_rec; ++j) B[j] = j;
+    }
+    int64_t r = p < q ? p : q;
+    for (int64_t j = 0; j < r; ++j)
+        for (int32_t a = 0; a < n_attrs; ++a)
+            attr[a][A[j]] = rec[a][B[j]];
+    if (applied) *applied = r;
+    if (dropped) *dropped = q - r;
+    free(A); free(B);
+}
+
+/* add_agents: the free slots are those with alive == 0; newborn j goes to the
+ * j-th lowest free slot (select_update on the free mask) and that slot becomes
+ * live.  Newborns beyond the number of free slots are dropped. */
+ORC_API void orc_add_agents(int64_t n, int32_t n_attrs, int32_t* const* attr, int32_t* alive,
+                            int64_t n_new, const int32_t* const* rec,
+                            int64_t* added, int64_t* dropped)
+{
+    uint8_t* freem = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    int64_t* F = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) freem[i] = (uint8_t)(alive[i] == 0);
+    int64_t nf = orc_select_indices(freem, n, F);
+    int64_t r = nf < n_new ? nf : n_new;
+    orc_select_update(n, n_attrs, attr, freem, n_new, rec, NULL, NULL, NULL);
+    for (int64_t j = 0; j < r; ++j) alive[F[j]] = 1;
+    if (added) *added = r;
+    if (dropped) *dropped = n_new - r;
+    free(freem); free(F);
+}
+
+/* remove_agents (set_agents_mask, Sec. 2): an independent masked update.
+ * removed = #{i : kill[i] and alive[i]}; then alive[i] = 0 wherever kill[i].
+ * The other fields of a removed slot are left as they were. */
+ORC_API void orc_remove_agents(int64_t n, int32_t* alive, const uint8_t* kill, int64_t* removed)
+{
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (kill[i]) {
+            if (alive[i]) ++cnt;
+            alive[i] = 0;
+        }
+    }
+    if (removed) *removed = cnt;
+}
+
+/* Conflict resolution (Sec. 5.2: a priority per claimant of a cell).  Claim c
+ * is active when active is NULL or active[c] != 0, and its target lies in
+ * [0, n_targets); other claims are ignored.  key_c = prio_c * 2^32 + c.
+ * best[t] = the minimum key over active claims on t (UINT64_MAX if none),
+ * winner[t] = the claim index of best[t] (-1 if none),
+ * won[c] = 1 exactly for the claim whose key is best[target_c]. */
+ORC_API void orc_resolve_conflicts(int64_t n_claims, const int32_t* target, const uint32_t* prio,
+                                   const uint8_t* active, int64_t n_targets,
+                                   uint64_t* best, int32_t* winner, uint8_t* won)
+{
+    for (int64_t t = 0; t < n_targets; ++t) best[t] = UINT64_MAX;
+    for (int64_t c = 0; c < n_claims; ++c) {
+        if (active && !active[c]) continue;
+        if (target[c] < 0 || (int64_t)target[c] >= n_targets) continue;
+        uint64_t key = ((uint64_t)prio[c] << 32) | (uint64_t)(uint32_t)c;
+        if (key < best[target[c]]) best[target[c]] = key;
+    }
+    for (int64_t t = 0; t < n_targets; ++t)
+        winner[t] = best[t] == UINT64_MAX ? -1 : (int32_t)(uint32_t)(best[t] & 0xFFFFFFFFULL);
+    for (int64_t c = 0; c < n_claims; ++c) {
+        won[c] = 0;
+        if (active && !active[c]) continue;
+        if (target[c] < 0 || (int64_t)target[c] >= n_targets) continue;
+        uint64_t key = ((uint64_t)prio[c] << 32) | (uint64_t)(uint32_t)c;
+        won[c] = (uint8_t)(best[target[c]] == key);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* 4. Predation model (Sec. 5.1, Fig. 2; Wilensky's wolf-sheep-grass).         */
+/* ------------------------------------------------------------------------- */
+
+/* draw purposes */
+enum {
+    P_GRASS_GROWN = 0x01, P_GRASS_CD = 0x02,
+    P_S_X = 0x10, P_S_Y = 0x11, P_S_E = 0x12, P_S_MOVE = 0x13,
+    P_S_GRASS_KEY = 0x14, P_S_PREY_KEY = 0x15, P_S_BREED = 0x16,
+    P_W_X = 0x20, P_W_Y = 0x21, P_W_E = 0x22, P_W_MOVE = 0x23,
+    P_W_EAT_KEY = 0x24, P_W_BREED = 0x26
+};
+#define STEP_INIT 0xFFFFFFFFu
+
+typedef struct {
+    int32_t W, H;        /* toroidal lattice */
+    int32_t R;           /* grass regrowth delay in steps */
+    int32_t gain_s, gain_w;
+    uint32_t T_s, T_w;   /* reproduction: draw < T */
+    uint32_t seed;
+    int64_t cap_s, cap_w; /* slot capacities */
+    int64_t n_s0, n_w0;   /* initial live counts */
+} orc_pred_params;
+
+typedef struct { int32_t *x, *y, *e, *alive; } orc_species;
+
+typedef struct {
+    int32_t* grass;       /* W*H countdown, 0 = grown; cell c = y*W + x */
+    orc_species sheep, wolves;
+    uint32_t step;        /* index of the next step to run */
+} orc_pred_state;
+
+typedef struct {
+    int64_t live_s, live_w;       /* at the start of the step */
+    int64_t grass_eaten, sheep_eaten;
+    int64_t births_s, births_w;
+    int64_t starved_s, starved_w;
+} orc_pred_stats;
+
+/* the eight neighbour offsets, indexed by the top three bits of a draw */
+static const int32_t DX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+static const int32_t DY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+
+static void init_species(const orc_pred_params* P, orc_species* s, int64_t cap, int64_t n0,
+                         uint32_t px, uint32_t py, uint32_t pe, int32_t gain)
+{
+    for (int64_t i = 0; i < cap; ++i) {
+        if (i < n0) {
+            s->x[i] = (int32_t)orc_uniform(orc_rng(P->seed, STEP_INIT, (uint32_t)i, px), (uint32_t)P->W);
+            s->y[i] = (int32_t)orc_uniform(orc_rng(P->seed, STEP_INIT, (uint32_t)i, py), (uint32_t)P->H);
+            s->e[i] = (int32_t)orc_uniform(orc_rng(P->seed, STEP_INIT, (uint32_t)i, pe), (uint32_t)(2 * gain));
+            s->alive[i] = 1;
+        } else {
+            s->x[i] = 0; s->y[i] = 0; s->e[i] = 0; s->alive[i] = 0;
+        }
+    }
+}
+
+/* Initial state: each cell is grown with probability 1/2 (draw < 2^31), else
+ * it carries a countdown uniform in [1, R].  Agents occupy slots 0..n0-1 at
+ * uniform cells with energy uniform in [0, 2*gain); other slots are zero. */
+ORC_API void orc_predation_init(const orc_pred_params* P, orc_pred_state* S)
+{
+    int64_t G = (int64_t)P->W * P->H;
+    for (int64_t c = 0; c < G; ++c) {
+        uint32_t h = orc_rng(P->seed, STEP_INIT, (uint32_t)c, P_GRASS_GROWN);
+        if (h < 0x80000000u)
+            S->grass[c] = 0;
+        else
+            S->grass[c] = 1 + (int32_t)orc_uniform(orc_rng(P->seed, STEP_INIT, (uint32_t)c, P_GRASS_CD),
+                                                   (uint32_t)P->R);
+    }
+    init_species(P, &S->sheep, P->cap_s, P->n_s0, P_S_X, P_S_Y, P_S_E, P->gain_s);
+    init_species(P, &S->wolves, P->cap_w, P->n_w0, P_W_X, P_W_Y, P_W_E, P->gain_w);
+    S->step = 0;
+}
+
+static int64_t count_live(const orc_species* s, int64_t cap)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < cap; ++i) k += s->alive[i] != 0;
+    return k;
+}
+
+/* Phase 1: every live agent steps to one of its eight neighbours (toroidal)
+ * and pays one unit of energy. */
+static void move_species(const orc_pred_params* P, orc_species* s, int64_t cap, uint32_t t, uint32_t purpose)
+{
+    for (int64_t i = 0; i < cap; ++i) {
+        if (!s->alive[i]) continue;
+        uint32_t d = orc_rng(P->seed, t, (uint32_t)i, purpose) >> 29;
+        s->x[i] = (s->x[i] + DX[d] + P->W) % P->W;
+        s->y[i] = (s->y[i] + DY[d] + P->H) % P->H;
+        s->e[i] -= 1;
+    }
+}
+
+static uint64_t agent_key(uint32_t seed, uint32_t t, int64_t i, uint32_t purpose)
+{
+    return ((uint64_t)orc_rng(seed, t, (uint32_t)i, purpose) << 32) | (uint64_t)(uint32_t)i;
+}
+
+/* Phase 3: breeders are live agents with positive energy whose draw is below
+ * T; free slots are those with alive == 0 (after eating).  The j-th breeder
+ * (ascending slot) puts a child on its own cell into the j-th lowest free
+ * slot; the child takes e >> 1 and the parent keeps e - (e >> 1).  Breeders
+ * beyond the number of free slots are unchanged. */
+static int64_t breed_species(const orc_pred_params* P, orc_species* s, int64_t cap, uint32_t t,
+                             uint32_t purpose, uint32_t T)
+{
+    int64_t* B = (int64_t*)malloc((size_t)(cap > 0 ? cap : 1) * sizeof(int64_t));
+    int64_t* F = (int64_t*)malloc((size_t)(cap > 0 ? cap : 1) * sizeof(int64_t));
+    int64_t nb = 0, nf = 0;
+    for (int64_t i = 0; i < cap; ++i) {
+        if (s->alive[i] && s->e[i] > 0 && orc_rng(P->seed, t, (uint32_t)i, purpose) < T) B[nb++] = i;
+        if (!s->alive[i]) F[nf++] = i;
+    }
+    int64_t r = nb < nf ? nb : nf;
+    for (int64_t j = 0; j < r; ++j) {
+        int64_t par = B[j], ch = F[j];
+        int32_t ec = s->e[par] >> 1;
+        s->x[ch] = s->x[par];
+        s->y[ch] = s->y[par];
+        s->e[ch] = ec;
+        s->e[par] = s->e[par] - ec;
+        s->alive[ch] = 1;
+    }
+    free(B); free(F);
+    return r;
+}
+
+/* Phase 4: live agents with negative energy die; their other fields stay. */
+static int64_t starve_species(orc_species* s, int64_t cap)
+{
+    int64_t k = 0;
+    for (int64_t i = 0; i < cap; ++i)
+        if (s->alive[i] && s->e[i] < 0) { s->alive[i] = 0; ++k; }
+    return k;
+}
+
+/* The five phases of step t = S->step, exported one by one so that tests can
+ * check each phase on its own; orc_predation_step runs them in order. */
+
+/* Phase 1 for both species. */
+ORC_API void orc_pred_move(const orc_pred_params* P, orc_pred_state* S)
+{
+    move_species(P, &S->sheep, P->cap_s, S->step, P_S_MOVE);
+    move_species(P, &S->wolves, P->cap_w, S->step, P_W_MOVE);
+}
+
+/* Phase 2.  Grass first: on every grown cell holding live sheep the sheep with
+ * the lowest key (draw << 32 | slot) eats it (energy += gain_s, countdown = R).
+ * Then prey: on every cell holding both live sheep and live wolves, the
+ * lowest-key sheep is eaten by the lowest-key wolf (energy += gain_w).  So at
+ * most one grass and one sheep are consumed per cell per step. */
+ORC_API void orc_pred_eat(const orc_pred_params* P, orc_pred_state* S,
+                          int64_t* grass_eaten, int64_t* sheep_eaten)
+{
+    const uint32_t t = S->step;
+    const int64_t G = (int64_t)P->W * P->H;
+    uint64_t* best = (uint64_t*)malloc((size_t)G * sizeof(uint64_t));
+    uint64_t* best2 = (uint64_t*)malloc((size_t)G * sizeof(uint64_t));
+    int64_t ng = 0, ns = 0;
+
+    for (int64_t c = 0; c < G; ++c) best[c] = UINT64_MAX;
+    for (int64_t i = 0; i < P->cap_s; ++i) {
+        if (!S->sheep.alive[i]) continue;
+        int64_t c = (int64_t)S->sheep.y[i] * P->W + S->sheep.x[i];
+        if (S->grass[c] != 0) continue;
+        uint64_t k = agent_key(P->seed, t, i, P_S_GRASS_KEY);
+        if (k < best[c]) best[c] = k;
+    }
+    for (int64_t c = 0; c < G; ++c) {
+        if (best[c] == UINT64_MAX) continue;
+        int64_t w = (int64_t)(uint32_t)(best[c] & 0xFFFFFFFFULL);
+        S->sheep.e[w] += P->gain_s;
+        S->grass[c] = P->R;
+        ++ng;
+    }
+
+    for (int64_t c = 0; c < G; ++c) { best[c] = UINT64_MAX; best2[c] = UINT64_MAX; }
+    for (int64_t i = 0; i < P->cap_s; ++i) {
+        if (!S->sheep.alive[i]) continue;
+        int64_t c = (int64_t)S->sheep.y[i] * P->W + S->sheep.x[i];
+        uint64_t k = agent_key(P->seed, t, i, P_S_PREY_KEY);
+        if (k < best[c]) best[c] = k;
+    }
+    for (int64_t j = 0; j < P->cap_w; ++j) {
+        if (!S->wolves.alive[j]) continue;
+        int64_t c = (int64_t)S->wolves.y[j] * P->W + S->wolves.x[j];
+        uint64_t k = agent_key(P->seed, t, j, P_W_EAT_KEY);
+        if (k < best2[c]) best2[c] = k;
+    }
+    for (int64_t c = 0; c < G; ++c) {
+        if (best[c] == UINT64_MAX || best2[c] == UINT64_MAX) continue;
+        int64_t prey = (int64_t)(uint32_t)(best[c] & 0xFFFFFFFFULL);
+        int64_t wolf = (int64_t)(uint32_t)(best2[c] & 0xFFFFFFFFULL);
+        S->sheep.alive[prey] = 0;
+        S->wolves.e[wolf] += P->gain_w;
+        ++ns;
+    }
+    free(best); free(best2);
+    if (grass_eaten) *grass_eaten = ng;
+    if (sheep_eaten) *sheep_eaten = ns;
+}
+
+/* Phase 3 for both species. */
+ORC_API void orc_pred_breed(const orc_pred_params* P, orc_pred_state* S,
+                            int64_t* births_s, int64_t* births_w)
+{
+    int64_t bs = breed_species(P, &S->sheep, P->cap_s, S->step, P_S_BREED, P->T_s);
+    int64_t bw = breed_species(P, &S->wolves, P->cap_w, S->step, P_W_BREED, P->T_w);
+    if (births_s) *births_s = bs;
+    if (births_w) *births_w = bw;
+}
+
+/* Phase 4 for both species. */
+ORC_API void orc_pred_die(const orc_pred_params* P, orc_pred_state* S,
+                          int64_t* starved_s, int64_t* starved_w)
+{
+    int64_t ss = starve_species(&S->sheep, P->cap_s);
+    int64_t sw = starve_species(&S->wolves, P->cap_w);
+    if (starved_s) *starved_s = ss;
+    if (starved_w) *starved_w = sw;
+}
+
+/* Phase 5: every countdown above zero drops by one, so a cell eaten at step t
+ * is grown again at step t + R. */
+ORC_API void orc_pred_regrow(const orc_pred_params* P, orc_pred_state* S)
+{
+    const int64_t G = (int64_t)P->W * P->H;
+    for (int64_t c = 0; c < G; ++c)
+        if (S->grass[c] > 0) S->grass[c] -= 1;
+}
+
+/* One step t = S->step in the order move, eat, breed, die, regrow; then the
+ * step counter advances.  Statistics of the step go to *st when given. */
+ORC_API void orc_predation_step(const orc_pred_params* P, orc_pred_state* S, orc_pred_stats* st)
+{
+    orc_pred_stats loc;
+    memset(&loc, 0, sizeof loc);
+    loc.live_s = count_live(&S->sheep, P->cap_s);
+    loc.live_w = count_live(&S->wolves, P->cap_w);
+    orc_pred_move(P, S);
+    orc_pred_eat(P, S, &loc.grass_eaten, &loc.sheep_eaten);
+    orc_pred_breed(P, S, &loc.births_s, &loc.births_w);
+    orc_pred_die(P, S, &loc.starved_s, &loc.starved_w);
+    orc_pred_regrow(P, S);
+    S->step += 1;
+    if (st) *st = loc;
+}
+
+/* Run n_steps steps; per-step statistics go to stats[0..n_steps) if given. */
+ORC_API void orc_predation_run(const orc_pred_params* P, orc_pred_state* S, int32_t n_steps,
+                               orc_pred_stats* stats)
+{
+    for (int32_t k = 0; k < n_steps; ++k)
+        orc_predation_step(P, S, stats ? &stats[k] : NULL);
+}
