@@ -1,0 +1,219 @@
+"""Benchmark of the select/update hot path on one MI355X.
+
+Workload (one "step"): the select_update microbenchmark -- 2^24 agent slots x
+8 int32 attributes in struct-of-arrays layout -- at the three mask densities
+p in {0.001, 0.05, 0.5}.  For each density a step runs
+  select_update  k = popcount(mask) distinct records into the selected slots,
+  add_agents     k newborns into the free slots of alive = 1 - mask,
+  remove_agents  kill mask = the same mask over the now all-live population
+                 (which restores alive, so every step does identical work).
+Ten seeded input sets (seeds 0-9) are resident in HBM and rotated step by step,
+so the 256 MB last-level cache cannot hold a step's inputs from one use to
+the next.  value = agent updates per second = (sum over densities of
+3 * k) / (time per step).
+
+Also printed: the HBM roofline of the dominant kernel (algorithmic bytes per
+launch / mean launch time from HIP events on the launch stream) and the CPU
+oracle timed on this host over a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "agent-updates/s + %HBM peak, batched vs plain per-model launch; p99 latency"
+N_SLOTS = 1 << 24
+N_ATTRS = 8
+
+
+def algorithmic_bytes(op, n, k):
+    """Bytes the method must move per launch (see the roofline model)."""
+    if op == "select_update":      # mask everywhere, k records read, k slots x 8 attrs written
+        return n + 64 * k
+    if op == "add_agents":         # alive everywhere, records read/written, alive set
+        return 4 * n + 68 * k
+    if op == "remove_agents":      # mask everywhere, alive read + written where killed
+        return n + 8 * k
+    raise ValueError(op)
+
+
+def _profile_traffic(kernel_sources_hash):
+    """HBM traffic per launch of the dominant kernel from the committed PMC
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "select_update_microbench_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_sources_hash:
+        return None
+    return float(t.group(1))
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2508_16508_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(sample_seconds):
+    """The oracle as it stands, single-threaded, on seed 0's inputs."""
+    import oracle
+    from paper_2508_16508_amd import workloads as W
+    cases = [W.select_update_case(0, p) for p in W.DENSITIES]
+    reps, updates, t0 = 0, 0, time.perf_counter()
+    while True:
+        for c in cases:
+            alive = (1 - c.mask).astype(np.int32)
+            out, applied, _ = oracle.select_update(c.attrs, c.mask, c.records)
+            out, al, added, _ = oracle.add_agents(out, alive, c.records)
+            al, removed = oracle.remove_agents(al, c.mask)
+            updates += applied + added + removed
+        reps += 1
+        if time.perf_counter() - t0 >= sample_seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "agent-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} step(s) of seed 0: select_update + add_agents + remove_agents at "
+                      f"p in {{0.001, 0.05, 0.5}}, 2^24 x 8 int32, single-threaded C oracle "
+                      f"via its ctypes wrapper ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sets", type=int, default=10, help="rotated input sets (seeds 0..sets-1)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2508_16508_amd as abm
+    from paper_2508_16508_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    # ---- resident inputs: per seed and density, mask + records + alive
+    sets = []
+    for seed in range(args.sets):
+        per_p = []
+        for p in W.DENSITIES:
+            c = W.select_update_case(seed, p, with_attrs=False)
+            mask = torch.from_numpy(c.mask).to(dev)
+            per_p.append(dict(p=p, k=c.k, mask=mask, rec=torch.from_numpy(c.records).to(dev),
+                              alive=(1 - mask).to(torch.int32)))
+        sets.append(per_p)
+    dst = torch.zeros((N_ATTRS, N_SLOTS), dtype=torch.int32, device=dev)
+    ws = abm.workspace(N_SLOTS, abm.ABM_OP_SELECT_UPDATE, dev)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    ops = ("select_update", "add_agents", "remove_agents")
+    events = {op: [] for op in ops}
+
+    def step(s, timed):
+        for d in sets[s % len(sets)]:
+            for op in ops:
+                if timed:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                if op == "select_update":
+                    abm.select_update(dst, d["mask"], d["rec"], ws=ws, applied=cnt[0:1],
+                                      dropped=cnt[1:2])
+                elif op == "add_agents":
+                    abm.add_agents(dst, d["alive"], d["rec"], ws=ws, added=cnt[2:3],
+                                   dropped=cnt[3:4])
+                else:
+                    abm.remove_agents(d["alive"], d["mask"], ws=ws, removed=cnt[4:5])
+                if timed:
+                    e1.record(stream)
+                    events[op].append((e0, e1, d["k"]))
+
+    for s in range(args.warmup):
+        step(s, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for s in range(args.steps):
+        step(args.warmup + s, True)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = g0.elapsed_time(g1)
+    ms_per_step = ms_total / args.steps
+
+    # correctness of the timed work: the last density's counts and restored alive
+    last = sets[(args.warmup + args.steps - 1) % len(sets)][-1]
+    c = cnt.cpu().numpy()
+    assert c[0] == last["k"] and c[1] == 0 and c[2] == last["k"] and c[4] == last["k"], c
+    assert int((last["alive"] == 0).sum().item()) == last["k"]
+
+    updates = 0
+    for s in range(args.steps):
+        updates += sum(3 * d["k"] for d in sets[(args.warmup + s) % len(sets)])
+    value = updates / (ms_total / 1e3)
+
+    kernels = {}
+    for op in ops:
+        durs = [e0.elapsed_time(e1) * 1e-3 for e0, e1, _ in events[op]]
+        byts = [algorithmic_bytes(op, N_SLOTS, k) for _, _, k in events[op]]
+        mean_s = float(np.mean(durs))
+        kernels[op] = dict(launches=len(durs), mean_us=mean_s * 1e6, total_ms=sum(durs) * 1e3,
+                           bytes_per_launch=float(np.mean(byts)),
+                           gbs=float(np.mean(byts)) / mean_s / 1e9)
+    dom = max(ops, key=lambda o: kernels[o]["total_ms"])
+    kd = kernels[dom]
+    src_hash = kernel_sources_hash()
+    traffic = _profile_traffic(src_hash) if dom == "select_update" else None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
+                "mean_launch_us": kd["mean_us"]}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "agent-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "select_update microbench (2^24 slots x 8 int32 SoA; "
+                               "select_update + add_agents + remove_agents at p in "
+                               "{0.001, 0.05, 0.5}; seeds 0-9 resident and rotated)",
+                   "slots": N_SLOTS, "attrs": N_ATTRS, "densities": list(W.DENSITIES),
+                   "input_sets": args.sets, "wall_s": wall},
+        "roofline": roofline,
+        "kernels": kernels,
+        "kernel_sources": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        del sets, dst
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * abm.h -- C ABI of libabm.so, an MI355X (gfx950) implementation of the ABMax
+ * hot path (arXiv 2508.16508): distinct updates to a dynamically selected,
+ * variable-size subset of agents held in fixed-capacity struct-of-arrays
+ * slots, and the wolf-sheep-grass predation step built on it.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers are DEVICE pointers unless marked (host).  Structs passed by
+ *    pointer (abm_soa, abm_records, parameter blocks) live in host memory and
+ *    are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call is asynchronous on that stream and never synchronises the
+ *    device; counts are written to device scalars so a caller reads them when
+ *    it chooses.  Calls sharing a workspace must be ordered on one stream.
+ *  - The caller owns every buffer.  The library keeps no pointer after a call
+ *    returns and allocates nothing in these calls.
+ *  - Status codes: ABM_OK, or a negative code with a message available from
+ *    abm_last_error() (thread-local).  Argument errors are detected on the host
+ *    before anything is launched, so a failed call has no effect.
+ *  - Masks are uint8 arrays: a non-zero byte selects.  `alive` arrays are
+ *    int32: non-zero = live slot, 0 = free placeholder slot (Sec. 4: shapes stay
+ *    fixed, unused capacity is held by placeholder agents).
+ *  - Sizes: capacities, counts and grids must be below 2^31.
+ */
+#ifndef ABM_H
+#define ABM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABM_MAX_ATTRS 16
+
+#if defined(__GNUC__)
+#define ABM_API __attribute__((visibility("default")))
+#else
+#define ABM_API
+#endif
+
+enum {
+    ABM_OK = 0,
+    ABM_E_INVALID = -1,     /* bad argument (NULL pointer, size out of range, mismatch) */
+    ABM_E_WORKSPACE = -2,   /* workspace missing or smaller than abm_workspace_bytes() */
+    ABM_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    ABM_E_UNSUPPORTED = -4  /* current device is not gfx950 */
+};
+
+/* A collection of agents (the paper's Set, Sec. 2): n_attrs int32 attribute
+ * arrays, each of `capacity` elements (struct of arrays), plus an optional
+ * `alive` array of `capacity` int32.  Attribute arrays must not alias each
+ * other, the alive array, or any record/mask argument of the same call. */
+typedef struct abm_soa {
+    int32_t n_attrs;                 /* 1..ABM_MAX_ATTRS */
+    int64_t capacity;                /* number of slots, 0 <= capacity < 2^31 */
+    int32_t* attr[ABM_MAX_ATTRS];    /* device, attr[a][slot] */
+    int32_t* alive;                  /* device, may be NULL where not used */
+} abm_soa;
+
+/* Dense update records, struct of arrays: record j is (attr[0][j], ...). */
+typedef struct abm_records {
+    int32_t n_attrs;                 /* must equal the destination's n_attrs */
+    int64_t count;                   /* m, 0 <= m < 2^31 */
+    const int32_t* attr[ABM_MAX_ATTRS];
+} abm_records;
+
+/* Operations, for abm_workspace_bytes(). */
+enum {
+    ABM_OP_SELECT_UPDATE = 1,
+    ABM_OP_ADD_AGENTS = 2,
+    ABM_OP_REMOVE_AGENTS = 3,
+    ABM_OP_SELECT_INDICES = 4,
+    ABM_OP_PREDATION = 5
+};
+
+/* Bytes of workspace `op` needs for `capacity` slots (for ABM_OP_SELECT_UPDATE
+ * with an update mask, pass capacity = max(slots, records)).  For
+ * ABM_OP_PREDATION pass capacity = max(cap_s, cap_w).  A larger workspace is
+ * always accepted; one workspace sized for the largest use serves every op. */
+ABM_API size_t abm_workspace_bytes(int op, int64_t capacity);
+
+/* Zero-fill a workspace before its first use (it holds the single-pass scan's
+ * tile ticket and tile status words, which later calls keep consistent).  Must
+ * be called once per workspace allocation, outside any graph capture. */
+ABM_API int abm_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * abm_select_update -- distinct updates to a dynamically selected subset.
+ * Sec. 4 (the toy task and the Rank-Match / Sort-Count-Iterate algorithms):
+ * p = number of selected slots, q = number of selected records, r = min(p, q);
+ * the j-th selected slot in ascending order receives every attribute of the
+ * j-th selected record in ascending order, for j < r.  Nothing else changes.
+ *
+ *   dst        destination collection (alive not used).
+ *   sel_mask   device uint8[dst->capacity], non-zero = slot selected.
+ *   upd        records; upd->n_attrs == dst->n_attrs.
+ *   upd_mask   NULL: all upd->count records are selected (q = count).
+ *              else device uint8[upd->count], non-zero = record selected.
+ *   d_applied  device int64: r.
+ *   d_dropped  device int64 or NULL: q - r (records that found no slot).
+ *   ws         workspace of at least abm_workspace_bytes(ABM_OP_SELECT_UPDATE,
+ *              max(capacity, upd->count)) bytes, initialised once.
+ * Applying the same call twice gives the same state as applying it once.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_select_update(const abm_soa* dst, const uint8_t* sel_mask, const abm_records* upd,
+                      const uint8_t* upd_mask, int64_t* d_applied, int64_t* d_dropped,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * abm_select_indices -- the paper's select_agents (Sec. 2): the ascending
+ * indices of the selected slots and their number.
+ *   mask       device uint8[n].
+ *   out_idx    device int32[n]; entries [0, k) are written, the rest untouched.
+ *   d_count    device int64: k.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_select_indices(const uint8_t* mask, int64_t n, int32_t* out_idx, int64_t* d_count,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * abm_add_agents -- new agents with distinct initial states (Sec. 1 and the
+ * Sec. 4 toy task applied to free slots): free slots are those with
+ * alive == 0; newborn j (record j) goes to the j-th lowest free slot, for
+ * j < min(#free, count), and that slot's alive becomes 1.
+ *   dst        collection; dst->alive required.
+ *   newborn    records, n_attrs == dst->n_attrs.
+ *   d_added    device int64: number placed.
+ *   d_dropped  device int64 or NULL: newborns that found no free slot.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_add_agents(const abm_soa* dst, const abm_records* newborn, int64_t* d_added,
+                   int64_t* d_dropped, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * abm_remove_agents -- the paper's set_agents_mask (Sec. 2): an independent,
+ * non-conflicting masked update.  alive[i] = 0 wherever kill_mask[i] != 0;
+ * other attributes of a removed slot are left as they were.
+ *   kill_mask  device uint8[dst->capacity].
+ *   d_removed  device int64: number of slots that were live and are now free.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_remove_agents(const abm_soa* dst, const uint8_t* kill_mask, int64_t* d_removed,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * abm_resolve_conflicts -- many claimants for one resource (Sec. 1; Sec. 5.2
+ * resolves competing moves with a priority per claimant).  Claim c is active
+ * when active == NULL or active[c] != 0, and its target lies in
+ * [0, n_targets); other claims are ignored.  With key_c = prio_c * 2^32 + c:
+ *   best[t]   = minimum key over active claims on t, or UINT64_MAX if none
+ *   winner[t] = claim index of best[t], or -1
+ *   won[c]    = 1 for the claim holding best[target_c], else 0.
+ * The lowest priority wins; equal priorities go to the lower claim index.
+ *   target    device int32[n_claims]; prio device uint32[n_claims];
+ *   active    device uint8[n_claims] or NULL;
+ *   best      device uint64[n_targets] (overwritten; no reset needed);
+ *   winner    device int32[n_targets]; won device uint8[n_claims].
+ * n_claims < 2^32.  No workspace.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_resolve_conflicts(int64_t n_claims, const int32_t* target, const uint32_t* prio,
+                          const uint8_t* active, int64_t n_targets, uint64_t* best,
+                          int32_t* winner, uint8_t* won, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Predation model (Sec. 5.1, Fig. 2: Wilensky's wolf-sheep-grass on a 2-D
+ * toroidal lattice).  Each step runs, in order:
+ *   move   every live agent steps to a uniformly drawn one of its 8 neighbours
+ *          and pays 1 energy;
+ *   eat    grass: on each grown cell holding live sheep, the sheep with the
+ *          lowest key (draw << 32 | slot) eats (+gain_s, countdown = R);
+ *          prey: on each cell holding live sheep and live wolves, the
+ *          lowest-key sheep is eaten by the lowest-key wolf (+gain_w);
+ *   breed  live agents with energy > 0 and draw < T reproduce: the j-th
+ *          breeder (ascending slot) puts a child on its own cell into the
+ *          j-th lowest free slot; child energy e >> 1, parent keeps the rest;
+ *   die    live agents with energy < 0 become free slots;
+ *   regrow every countdown above zero drops by one.
+ * Draws are hi32(mix64(mix64(seed << 32 | step) ^ (agent << 32 | purpose)))
+ * with mix64 the SplitMix64 output function, so a model resumes exactly from
+ * its state and step counter.
+ * ------------------------------------------------------------------------- */
+typedef struct abm_predation_params {
+    int32_t W, H;          /* lattice, cell = y * W + x; 1 <= W, H; W * H < 2^31 */
+    int32_t R;             /* regrowth delay in steps, >= 1 */
+    int32_t gain_s, gain_w;
+    uint32_t T_s, T_w;     /* reproduce when draw < T (floor(prob * 2^32)) */
+    uint32_t seed;
+    int64_t cap_s, cap_w;  /* slot capacities, 1 <= cap < 2^31 */
+    int64_t n_s0, n_w0;    /* initial live agents (slots 0 .. n0-1), n0 <= cap */
+} abm_predation_params;
+
+typedef struct abm_species {
+    int32_t* x;            /* device int32[cap] */
+    int32_t* y;
+    int32_t* e;            /* energy */
+    int32_t* alive;
+} abm_species;
+
+typedef struct abm_predation_state {
+    int32_t* grass;        /* device int32[W*H]: steps until regrown (0 = grown) */
+    abm_species sheep, wolves;
+    uint64_t* claims;      /* device uint64[3 * W*H], scratch owned by the caller */
+    int64_t* stats;        /* device int64[8 * n_steps] or NULL: per step
+                              live_s, live_w (at step start), grass_eaten,
+                              sheep_eaten, births_s, births_w, starved_s, starved_w */
+    uint32_t step;         /* (host) index of the next step; advanced by the call */
+} abm_predation_state;
+
+/* Fill the initial state: each cell grown with probability 1/2, else a
+ * countdown uniform in [1, R]; agents in slots 0 .. n0-1 at uniform cells with
+ * energy uniform in [0, 2 * gain); all other slots zero.  Sets s->step = 0. */
+ABM_API int abm_predation_init(const abm_predation_params* p, abm_predation_state* s, void* stream);
+
+/* Run n_steps steps starting at s->step, then advance s->step.  When
+ * s->stats is non-NULL, row k of it receives the statistics of step k of this
+ * call.  ws: abm_workspace_bytes(ABM_OP_PREDATION, max(cap_s, cap_w)). */
+ABM_API int abm_predation_step(const abm_predation_params* p, abm_predation_state* s, int32_t n_steps,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Message describing the last non-OK status returned on this thread. */
+ABM_API const char* abm_last_error(void);
+
+/* Library version string. */
+ABM_API const char* abm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABM_H */

@@ -1,0 +1,324 @@
+"""Python binding for libabm.so, the MI355X (gfx950) ABMax hot path.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libabm.so``; PyTorch supplies device memory and the current stream.  The
+names follow the C ABI in ``include/abm.h``.  Importing this package does not
+need a GPU; calling into it does, and a missing library is an error (there is
+no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libabm.so")
+
+ABM_MAX_ATTRS = 16
+ABM_OK, ABM_E_INVALID, ABM_E_WORKSPACE, ABM_E_HIP, ABM_E_UNSUPPORTED = 0, -1, -2, -3, -4
+ABM_OP_SELECT_UPDATE, ABM_OP_ADD_AGENTS, ABM_OP_REMOVE_AGENTS = 1, 2, 3
+ABM_OP_SELECT_INDICES, ABM_OP_PREDATION = 4, 5
+
+# Every symbol include/abm.h declares.
+EXPORTED = (
+    "abm_workspace_bytes", "abm_workspace_init", "abm_select_update", "abm_select_indices",
+    "abm_add_agents", "abm_remove_agents", "abm_resolve_conflicts", "abm_predation_init",
+    "abm_predation_step", "abm_last_error", "abm_version",
+)
+
+
+class AbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"abm status {code}: {msg}")
+        self.code = code
+
+
+class Soa(C.Structure):
+    _fields_ = [("n_attrs", C.c_int32), ("capacity", C.c_int64),
+                ("attr", C.c_void_p * ABM_MAX_ATTRS), ("alive", C.c_void_p)]
+
+
+class Records(C.Structure):
+    _fields_ = [("n_attrs", C.c_int32), ("count", C.c_int64),
+                ("attr", C.c_void_p * ABM_MAX_ATTRS)]
+
+
+class PredationParams(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("R", C.c_int32),
+                ("gain_s", C.c_int32), ("gain_w", C.c_int32),
+                ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
+                ("cap_s", C.c_int64), ("cap_w", C.c_int64),
+                ("n_s0", C.c_int64), ("n_w0", C.c_int64)]
+
+
+class SpeciesPtrs(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("e", C.c_void_p), ("alive", C.c_void_p)]
+
+
+class PredationStatePtrs(C.Structure):
+    _fields_ = [("grass", C.c_void_p), ("sheep", SpeciesPtrs), ("wolves", SpeciesPtrs),
+                ("claims", C.c_void_p), ("stats", C.c_void_p), ("step", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libabm.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+        L.abm_workspace_bytes.argtypes = [C.c_int, i64]
+        L.abm_workspace_bytes.restype = sz
+        L.abm_workspace_init.argtypes = [vp, sz, vp]
+        L.abm_select_update.argtypes = [C.POINTER(Soa), vp, C.POINTER(Records), vp, vp, vp, vp,
+                                        sz, vp]
+        L.abm_select_indices.argtypes = [vp, i64, vp, vp, vp, sz, vp]
+        L.abm_add_agents.argtypes = [C.POINTER(Soa), C.POINTER(Records), vp, vp, vp, sz, vp]
+        L.abm_remove_agents.argtypes = [C.POINTER(Soa), vp, vp, vp, sz, vp]
+        L.abm_resolve_conflicts.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.abm_predation_init.argtypes = [C.POINTER(PredationParams),
+                                         C.POINTER(PredationStatePtrs), vp]
+        L.abm_predation_step.argtypes = [C.POINTER(PredationParams),
+                                         C.POINTER(PredationStatePtrs), i32, vp, sz, vp]
+        L.abm_last_error.restype = C.c_char_p
+        L.abm_version.restype = C.c_char_p
+        for name in EXPORTED:
+            if name not in ("abm_workspace_bytes", "abm_last_error", "abm_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != ABM_OK:
+        raise AbmError(rc, lib().abm_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require(t, dtype, name):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _rows(t: torch.Tensor, name: str):
+    """Row pointers of a 2-D int32 tensor [n_attrs, length] (or a list of 1-D tensors)."""
+    if isinstance(t, (list, tuple)):
+        for r in t:
+            _require(r, torch.int32, name)
+        return [r.data_ptr() for r in t], (t[0].numel() if len(t) else 0)
+    _require(t, torch.int32, name)
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be [n_attrs, length]")
+    return [t[a].data_ptr() for a in range(t.shape[0])], t.shape[1]
+
+
+def make_soa(attrs, alive=None) -> Soa:
+    ptrs, n = _rows(attrs, "attrs")
+    s = Soa()
+    s.n_attrs = len(ptrs)
+    s.capacity = n if ptrs else (alive.numel() if alive is not None else 0)
+    for a, p in enumerate(ptrs):
+        s.attr[a] = p
+    _require(alive, torch.int32, "alive")
+    s.alive = alive.data_ptr() if alive is not None else None
+    return s
+
+
+def make_records(recs) -> Records:
+    ptrs, m = _rows(recs, "records")
+    r = Records()
+    r.n_attrs = len(ptrs)
+    r.count = m
+    for a, p in enumerate(ptrs):
+        r.attr[a] = p
+    return r
+
+
+def workspace_bytes(op: int, capacity: int) -> int:
+    return int(lib().abm_workspace_bytes(op, capacity))
+
+
+def workspace(capacity: int, op: int = ABM_OP_PREDATION, device=None, stream=None) -> torch.Tensor:
+    """Allocate and initialise a workspace big enough for `capacity` slots."""
+    nbytes = workspace_bytes(op, capacity)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off: off + nbytes]
+    _check(lib().abm_workspace_init(_p(ws), nbytes, _stream(stream)))
+    return ws
+
+
+def _counts(device, *given):
+    return [g if g is not None else torch.zeros(1, dtype=torch.int64, device=device) for g in given]
+
+
+def select_update(attrs, sel_mask, recs, upd_mask=None, ws=None, applied=None, dropped=None,
+                  stream=None):
+    """Distinct updates to the selected slots (Sec. 4).  Returns (applied, dropped)
+    as 1-element int64 device tensors; attrs is updated in place."""
+    dst = make_soa(attrs)
+    upd = make_records(recs)
+    _require(sel_mask, torch.uint8, "sel_mask")
+    _require(upd_mask, torch.uint8, "upd_mask")
+    dev = sel_mask.device
+    if ws is None:
+        ws = workspace(max(dst.capacity, upd.count), ABM_OP_SELECT_UPDATE, dev, stream)
+    applied, dropped = _counts(dev, applied, dropped)
+    _check(lib().abm_select_update(C.byref(dst), _p(sel_mask), C.byref(upd), _p(upd_mask),
+                                   _p(applied), _p(dropped), _p(ws), ws.numel(), _stream(stream)))
+    return applied, dropped
+
+
+def select_indices(mask, out_idx=None, ws=None, count=None, stream=None):
+    """Ascending indices of the selected entries (Sec. 2 select_agents).
+    Returns (out_idx int32[n], count int64[1]); entries [0, count) are valid."""
+    _require(mask, torch.uint8, "mask")
+    n = mask.numel()
+    dev = mask.device
+    if out_idx is None:
+        out_idx = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(n, ABM_OP_SELECT_INDICES, dev, stream)
+    (count,) = _counts(dev, count)
+    _check(lib().abm_select_indices(_p(mask), n, _p(out_idx), _p(count), _p(ws), ws.numel(),
+                                    _stream(stream)))
+    return out_idx, count
+
+
+def add_agents(attrs, alive, recs, ws=None, added=None, dropped=None, stream=None):
+    """Newborn j into the j-th lowest free slot.  Returns (added, dropped)."""
+    dst = make_soa(attrs, alive)
+    nb = make_records(recs)
+    dev = alive.device
+    if ws is None:
+        ws = workspace(dst.capacity, ABM_OP_ADD_AGENTS, dev, stream)
+    added, dropped = _counts(dev, added, dropped)
+    _check(lib().abm_add_agents(C.byref(dst), C.byref(nb), _p(added), _p(dropped), _p(ws),
+                                ws.numel(), _stream(stream)))
+    return added, dropped
+
+
+def remove_agents(alive, kill_mask, ws=None, removed=None, stream=None):
+    """alive[i] = 0 wherever kill_mask[i] (Sec. 2 set_agents_mask).  Returns removed."""
+    _require(alive, torch.int32, "alive")
+    _require(kill_mask, torch.uint8, "kill_mask")
+    s = Soa()
+    s.n_attrs = 0
+    s.capacity = alive.numel()
+    s.alive = alive.data_ptr()
+    dev = alive.device
+    if ws is None:
+        ws = workspace(alive.numel(), ABM_OP_REMOVE_AGENTS, dev, stream)
+    (removed,) = _counts(dev, removed)
+    _check(lib().abm_remove_agents(C.byref(s), _p(kill_mask), _p(removed), _p(ws), ws.numel(),
+                                   _stream(stream)))
+    return removed
+
+
+def resolve_conflicts(target, prio, n_targets, active=None, best=None, winner=None, won=None,
+                      stream=None):
+    """Lowest (prio, claim) wins each target.  Returns (best, winner, won)."""
+    _require(target, torch.int32, "target")
+    _require(prio, torch.int32 if prio.dtype == torch.int32 else torch.uint32, "prio")
+    _require(active, torch.uint8, "active")
+    n = target.numel()
+    dev = target.device
+    if best is None:
+        best = torch.empty(max(1, n_targets), dtype=torch.uint64, device=dev)
+    if winner is None:
+        winner = torch.empty(max(1, n_targets), dtype=torch.int32, device=dev)
+    if won is None:
+        won = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    _check(lib().abm_resolve_conflicts(n, _p(target), _p(prio), _p(active), n_targets, _p(best),
+                                       _p(winner), _p(won), _stream(stream)))
+    return best, winner, won
+
+
+# ---------------------------------------------------------------- predation
+
+@dataclass
+class PredationModel:
+    """Device-resident predation model (Sec. 5.1): grass countdown, per-species
+    SoA (x, y, energy, alive) and the per-cell claim tables."""
+    params: PredationParams
+    grass: torch.Tensor
+    sheep: dict
+    wolves: dict
+    claims: torch.Tensor
+    ws: torch.Tensor
+    step: int = 0
+
+    @staticmethod
+    def create(params: PredationParams, device="cuda", stream=None) -> "PredationModel":
+        G = params.W * params.H
+        z = lambda n: torch.empty(n, dtype=torch.int32, device=device)
+        sheep = {k: z(params.cap_s) for k in ("x", "y", "e", "alive")}
+        wolves = {k: z(params.cap_w) for k in ("x", "y", "e", "alive")}
+        claims = torch.empty(3 * G, dtype=torch.uint64, device=device)
+        ws = workspace(max(params.cap_s, params.cap_w), ABM_OP_PREDATION, device, stream)
+        return PredationModel(params, z(G), sheep, wolves, claims, ws)
+
+    def _ptrs(self, stats=None) -> PredationStatePtrs:
+        sp = lambda d: SpeciesPtrs(*(d[k].data_ptr() for k in ("x", "y", "e", "alive")))
+        return PredationStatePtrs(self.grass.data_ptr(), sp(self.sheep), sp(self.wolves),
+                                  self.claims.data_ptr(),
+                                  stats.data_ptr() if stats is not None else None, self.step)
+
+    def init(self, stream=None):
+        st = self._ptrs()
+        _check(lib().abm_predation_init(C.byref(self.params), C.byref(st), _stream(stream)))
+        self.step = int(st.step)
+
+    def run(self, n_steps: int, stats: torch.Tensor | None = None, stream=None):
+        """Advance n_steps; stats (int64 [n_steps, 8]) receives per-step counts."""
+        if stats is not None:
+            _require(stats, torch.int64, "stats")
+            assert stats.numel() >= 8 * n_steps
+        st = self._ptrs(stats)
+        _check(lib().abm_predation_step(C.byref(self.params), C.byref(st), n_steps,
+                                        _p(self.ws), self.ws.numel(), _stream(stream)))
+        self.step = int(st.step)
+
+
+def predation_params(W=64, H=64, R=30, gain_s=4, gain_w=20, T_s=171798691, T_w=214748364,
+                     seed=0, cap_s=4096, cap_w=1024, n_s0=400, n_w0=100) -> PredationParams:
+    """Defaults: the small 64x64 workload (regrowth 30, gains 4 / 20,
+    reproduction 0.04 / 0.05 as floor(p * 2^32))."""
+    return PredationParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0)
+
+
+def predation_init(params, model: PredationModel | None = None, device="cuda", stream=None):
+    m = model or PredationModel.create(params, device, stream)
+    m.init(stream)
+    return m
+
+
+def predation_step(model: PredationModel, n_steps: int = 1, stats=None, stream=None):
+    model.run(n_steps, stats, stream)
+    return model
+
+
+STAT_NAMES = ("live_s", "live_w", "grass_eaten", "sheep_eaten", "births_s", "births_w",
+              "starved_s", "starved_w")

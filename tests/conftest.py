@@ -22,3 +22,14 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def abm():
+    """The HIP library binding; builds libabm.so here if it is absent."""
+    import paper_2508_16508_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_2508_16508_amd import _build
+        _build.build()
+    pkg.lib()
+    return pkg

@@ -1,0 +1,117 @@
+"""The C-ABI boundary, checked without a GPU: the library loads, exports exactly
+the entry points include/abm.h declares, and rejects bad arguments on the host
+before anything is launched."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "abm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return set(re.findall(r"ABM_API\s+[\w\s\*]*?\b(abm_\w+)\s*\(", text))
+
+
+def test_header_declares_binding_names(abm):
+    assert _declared() == set(abm.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(abm):
+    out = subprocess.run(["nm", "-D", "--defined-only", abm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(abm_\w+)$", out, flags=re.M))
+    assert exported == _declared()
+    for name in _declared():
+        assert getattr(abm.lib(), name) is not None
+
+
+def test_library_is_gfx950_only(abm):
+    """The offload bundle of the library (built here) targets gfx950 only."""
+    blob = open(abm.LIB_PATH, "rb").read()
+    targets = set(re.findall(rb"amdgcn-amd-amdhsa-+(gfx\w+)", blob))
+    assert targets == {b"gfx950"}
+
+
+def test_workspace_bytes(abm):
+    small = abm.workspace_bytes(abm.ABM_OP_SELECT_UPDATE, 1)
+    big = abm.workspace_bytes(abm.ABM_OP_SELECT_UPDATE, 1 << 24)
+    assert 256 < small < big
+    assert abm.workspace_bytes(abm.ABM_OP_PREDATION, 1 << 24) == big
+    assert abm.workspace_bytes(999, 10) == 0
+    assert abm.lib().abm_version().decode().startswith("abm")
+
+
+def _err(abm):
+    return abm.lib().abm_last_error().decode()
+
+
+def test_invalid_arguments_rejected_on_host(abm):
+    L = abm.lib()
+    soa = abm.Soa()
+    rec = abm.Records()
+    # NULL collection
+    assert L.abm_select_update(None, None, C.byref(rec), None, None, None, None, 0, None) == \
+        abm.ABM_E_INVALID
+    assert "NULL" in _err(abm)
+    # attribute count out of range
+    soa.n_attrs, soa.capacity = 17, 10
+    assert L.abm_select_update(C.byref(soa), None, C.byref(rec), None, None, None, None, 0,
+                               None) == abm.ABM_E_INVALID
+    # mismatched record attribute count
+    soa.n_attrs, soa.capacity = 2, 0
+    rec.n_attrs, rec.count = 3, 0
+    assert L.abm_select_update(C.byref(soa), None, C.byref(rec), None, None, None, None, 0,
+                               None) == abm.ABM_E_INVALID
+    assert "differ" in _err(abm)
+    # capacity beyond 2^31
+    soa.n_attrs, soa.capacity, rec.n_attrs = 1, 1 << 31, 1
+    assert L.abm_add_agents(C.byref(soa), C.byref(rec), None, None, None, 0, None) == \
+        abm.ABM_E_INVALID
+    # add_agents needs alive
+    soa.capacity = 5
+    soa.attr[0] = 16
+    assert L.abm_add_agents(C.byref(soa), C.byref(rec), None, None, None, 0, None) == \
+        abm.ABM_E_INVALID
+    assert "alive" in _err(abm)
+    # remove: misaligned mask
+    soa.alive = 256
+    assert L.abm_remove_agents(C.byref(soa), C.c_void_p(3), C.c_void_p(256), None, 0, None) == \
+        abm.ABM_E_INVALID
+    assert "aligned" in _err(abm)
+    # resolve: negative sizes
+    assert L.abm_resolve_conflicts(-1, None, None, None, 4, None, None, None, None) == \
+        abm.ABM_E_INVALID
+    assert L.abm_resolve_conflicts(4, None, None, None, 4, None, None, None, None) == \
+        abm.ABM_E_INVALID
+    # select_indices: missing count
+    assert L.abm_select_indices(None, 0, None, None, None, 0, None) == abm.ABM_E_INVALID
+    # workspace init with nothing
+    assert L.abm_workspace_init(None, 0, None) == abm.ABM_E_WORKSPACE
+
+
+def test_invalid_predation_params_rejected_on_host(abm):
+    L = abm.lib()
+    st = abm.PredationStatePtrs()
+    for bad in (dict(W=0), dict(R=0), dict(cap_s=0), dict(n_s0=5000), dict(gain_w=-1),
+                dict(W=1 << 16, H=1 << 16)):
+        p = abm.predation_params(**bad)
+        assert L.abm_predation_init(C.byref(p), C.byref(st), None) == abm.ABM_E_INVALID, bad
+    p = abm.predation_params()
+    # NULL state arrays
+    assert L.abm_predation_step(C.byref(p), C.byref(st), 1, None, 0, None) == abm.ABM_E_INVALID
+    assert L.abm_predation_step(C.byref(p), None, 1, None, 0, None) == abm.ABM_E_INVALID
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    """No CPU fallback: a missing libabm.so is an ImportError at first use."""
+    import paper_2508_16508_amd as pkg
+    monkeypatch.setattr(pkg, "_lib", None)
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        pkg.lib()
