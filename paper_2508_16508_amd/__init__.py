@@ -170,6 +170,12 @@ def workspace(capacity: int, op: int = ABM_OP_PREDATION, device=None, stream=Non
     return ws
 
 
+def workspace_error(ws: torch.Tensor) -> int:
+    """The workspace error word: non-zero if a bounded wait inside a kernel ever
+    gave up (the single-pass scan's ordering assumption failed).  Synchronises."""
+    return int(ws[248:256].view(torch.int64).item())
+
+
 def _counts(device, *given):
     return [g if g is not None else torch.zeros(1, dtype=torch.int64, device=device) for g in given]
 

@@ -47,6 +47,36 @@ int check_device() {
     return ABM_OK;
 }
 
+namespace {
+std::atomic<uint32_t> g_host_epoch{1};
+
+__global__ void k_bump_epoch(uint32_t* word) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t e = *word & 0x1FFFFFFFu;
+        *word = ((e + 1u) & 0x1FFFFFFFu) | 0x20000000u;
+    }
+}
+}  // namespace
+
+int next_epoch(const Workspace& w, hipStream_t st, EpochArg* out) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) {
+        set_error("hipStreamIsCapturing: %s", hipGetErrorString(e));
+        return ABM_E_HIP;
+    }
+    if (cs == hipStreamCaptureStatusActive) {
+        uint32_t* word = reinterpret_cast<uint32_t*>(w.hdr + kHdrEpoch);
+        hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(64), 0, st, word);
+        out->value = 0;
+        out->dev = word;
+        return launch_status("epoch");
+    }
+    out->value = g_host_epoch.fetch_add(1, std::memory_order_relaxed) & 0x1FFFFFFFu;
+    out->dev = nullptr;
+    return ABM_OK;
+}
+
 }  // namespace abm
 
 extern "C" {

@@ -38,21 +38,22 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // ---------------------------------------------------------------- workspace
 // [0, 256)                 header words (uint64); the last one is the scan
 //                          error word, directly before the status array
-// [256, 256 + 8*T)         tile status words of the single-pass scans
+// [256, 256 + 8*S)         tile status words of the single-pass scans
 // [.., + 4*C)              int32 index list (compacted record indices or breeders)
 // [.., + 4*C)              second int32 index list (second species)
-// The status area covers two chains of ceil(C / kMinTile) tiles each.
+// [.., + 8*kAccWords)      int64 spread accumulators (kAccLanes per counter)
+// S covers two chains of ceil(C / kMinTile) tiles each.
 constexpr int64_t kHeaderBytes = 256;
 constexpr int64_t kMinTile = 512;
+constexpr int kAccLanes = 256;             // accumulators per counter
+constexpr int kAccCounters = 8;
+constexpr int64_t kAccWords = int64_t(kAccLanes) * kAccCounters;
 
 enum HeaderWord : int {
-    kHdrTicket = 0,   // scan tile ticket (low 32 bits) and epoch (high 32 bits)
-    kHdrRemove = 1,   // remove_agents: blocks done (high) and removed count (low)
+    kHdrEpoch = 0,    // device epoch word (uint32 in the low half) for graph-recorded launches
     kHdrCountA = 2,   // int64 count produced on the device (selected records / breeders)
     kHdrCountB = 3,   // int64 second count (second species)
-    kHdrReduce = 4,   // generic done/sum reduction word
-    kHdrWords = 32,
-    kHdrError = 31    // set to 1 when a look-back wait gave up (never expected)
+    kHdrError = 31    // set to 1 when a bounded wait gave up (never expected)
 };
 
 inline int64_t tiles_for(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
@@ -61,7 +62,7 @@ inline int64_t status_words(int64_t capacity) { return 2 * tiles_for(capacity, k
 
 inline size_t workspace_bytes(int64_t capacity) {
     if (capacity < 1) capacity = 1;
-    return (size_t)(kHeaderBytes + 8 * status_words(capacity) + 8 * capacity + 64);
+    return (size_t)(kHeaderBytes + 8 * status_words(capacity) + 8 * capacity + 8 * kAccWords + 64);
 }
 
 struct Workspace {
@@ -69,6 +70,7 @@ struct Workspace {
     uint64_t* status;
     int32_t* list_a;
     int32_t* list_b;
+    int64_t* acc;
 };
 
 inline Workspace carve(void* ws, int64_t capacity) {
@@ -80,6 +82,7 @@ inline Workspace carve(void* ws, int64_t capacity) {
     char* lists = p + kHeaderBytes + 8 * status_words(capacity);
     w.list_a = reinterpret_cast<int32_t*>(lists);
     w.list_b = reinterpret_cast<int32_t*>(lists + 4 * capacity);
+    w.acc = reinterpret_cast<int64_t*>(lists + 8 * capacity);
     return w;
 }
 
@@ -97,5 +100,18 @@ inline int check_ws(const void* ws, size_t ws_bytes, int64_t capacity) {
 }
 
 constexpr int64_t kMaxIndex = (int64_t(1) << 31) - 1;
+
+}  // namespace abm
+
+#include "scan.hpp"
+
+namespace abm {
+
+// Epoch for the next single-pass launch on workspace w: a fresh host value
+// (launch argument), or -- when the stream is recording a graph, whose
+// arguments replay unchanged -- the device epoch word, advanced in-stream by
+// a one-thread kernel first.  Host epochs use bit 29 = 0 and device epochs
+// bit 29 = 1, so the two never coincide on one workspace.
+int next_epoch(const Workspace& w, hipStream_t st, EpochArg* out);
 
 }  // namespace abm

@@ -62,9 +62,10 @@ struct StepArgs {
     uint64_t* sclaim;     // prey: lowest sheep key per cell
     uint64_t* wclaim;     // eater: lowest wolf key per cell
     int64_t* stats;       // this step's row of 8, or null
+    int64_t* acc;         // kAccCounters x kAccLanes spread accumulators
     uint32_t step;
-    uint64_t* hdr;        // scan ticket word
     uint64_t* status;
+    EpochArg epoch;
     int32_t* blist[2];    // breeder lists
     int64_t* d_nb[2];     // breeder counts
     uint32_t tiles[2];
@@ -86,8 +87,11 @@ __device__ __forceinline__ uint64_t agent_key(uint64_t skey, int64_t slot, uint3
     return (uint64_t(draw(skey, uint32_t(slot), purpose)) << 32) | uint32_t(slot);
 }
 
-// Block-wide sum of one value per thread, added atomically to *dst by thread 0.
-__device__ __forceinline__ void block_add(uint32_t v, int64_t* dst, uint32_t* lds) {
+// Block-wide sum of one value per thread, added by thread 0 to this block's
+// lane of the spread accumulator of counter `col` (256 lanes per counter, so
+// no single address takes every block's atomic).
+__device__ __forceinline__ void block_add(uint32_t v, int64_t* acc, int col, uint32_t* lds) {
+    int64_t* dst = acc + int64_t(col) * kAccLanes + (blockIdx.x & (kAccLanes - 1));
     const uint32_t w = wave_sum(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = w;
@@ -181,24 +185,15 @@ __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
         }
     }
     if (a.stats) {
-        block_add(live_s, a.stats + kLiveS, lds);
-        block_add(live_w, a.stats + kLiveW, lds);
+        block_add(live_s, a.acc, kLiveS, lds);
+        block_add(live_w, a.acc, kLiveW, lds);
     }
 }
 
-// Takes a tile ticket and maps it to (species, tile within species).
-__device__ __forceinline__ void species_tile(const StepArgs& a, uint32_t* s_tile, uint32_t* s_epoch,
-                                             uint32_t& tile, uint32_t& epoch, int& s,
+// Maps workgroup t to (species, first tile of that species' scan chain).
+__device__ __forceinline__ void species_tile(const StepArgs& a, uint32_t& tile, int& s,
                                              uint32_t& seg_first) {
-    if (threadIdx.x == 0) {
-        uint32_t t, e;
-        take_ticket(a.hdr, a.tiles[0] + a.tiles[1], t, e);
-        *s_tile = t;
-        *s_epoch = e;
-    }
-    __syncthreads();
-    tile = *s_tile;
-    epoch = *s_epoch;
+    tile = blockIdx.x;
     s = tile < a.tiles[0] ? 0 : 1;
     seg_first = s ? a.tiles[0] : 0u;
 }
@@ -206,10 +201,10 @@ __device__ __forceinline__ void species_tile(const StepArgs& a, uint32_t* s_tile
 // ------------------------------------------------------------------ K2
 __global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ uint32_t s_tile, s_epoch;
-    uint32_t tile, epoch, seg_first;
+    uint32_t tile, seg_first;
     int s;
-    species_tile(a, &s_tile, &s_epoch, tile, epoch, s, seg_first);
+    species_tile(a, tile, s, seg_first);
+    const uint32_t epoch = read_epoch(a.epoch);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t base = int64_t(tile - seg_first) * kTile + int64_t(wave) * kItems * 64 + lane;
@@ -258,18 +253,18 @@ __global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
     const uint32_t last = seg_first + a.tiles[s] - 1;
     if (tile == last && threadIdx.x == 0) *a.d_nb[s] = int64_t(tile_excl) + total;
     if (a.stats && s == 0) {
-        block_add(grass_eaten, a.stats + kGrassEaten, lds);
-        block_add(sheep_eaten, a.stats + kSheepEaten, lds);
+        block_add(grass_eaten, a.acc, kGrassEaten, lds);
+        block_add(sheep_eaten, a.acc, kSheepEaten, lds);
     }
 }
 
 // ------------------------------------------------------------------ K3
 __global__ __launch_bounds__(kWaves * 64) void k_breed_die(StepArgs a) {
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ uint32_t s_tile, s_epoch;
-    uint32_t tile, epoch, seg_first;
+    uint32_t tile, seg_first;
     int s;
-    species_tile(a, &s_tile, &s_epoch, tile, epoch, s, seg_first);
+    species_tile(a, tile, s, seg_first);
+    const uint32_t epoch = read_epoch(a.epoch);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t base = int64_t(tile - seg_first) * kTile + int64_t(wave) * kItems * 64 + lane;
@@ -312,15 +307,32 @@ __global__ __launch_bounds__(kWaves * 64) void k_breed_die(StepArgs a) {
             const int64_t nfree = int64_t(tile_excl) + total;
             a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
         }
-        block_add(starved, a.stats + (s ? kStarvedW : kStarvedS), lds);
+        block_add(starved, a.acc, s ? kStarvedW : kStarvedS, lds);
     }
 }
 
 // ------------------------------------------------------------------ K4
+// Workgroup 0 also folds the step's spread accumulators into its stats row
+// and clears them for the next step (the births columns are written directly
+// by the breed kernel).
 __global__ __launch_bounds__(kBlock) void k_regrow_rearm(int32_t* __restrict__ grass,
                                                          uint64_t* __restrict__ claims, int64_t G,
-                                                         int do_regrow) {
+                                                         int do_regrow, int64_t* acc,
+                                                         int64_t* stats) {
     const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (stats && blockIdx.x == 0) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int col = wave; col < kAccCounters; col += kBlock / 64) {
+            int64_t v = 0;
+            for (int l = lane; l < kAccLanes; l += 64) {
+                v += acc[col * kAccLanes + l];
+                acc[col * kAccLanes + l] = 0;
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && col != kBirthsS && col != kBirthsW) stats[col] = v;
+        }
+    }
     if (c >= G) return;
     if (do_regrow) {
         const int32_t g = grass[c];
@@ -431,8 +443,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.gclaim = s->claims;
     a.sclaim = s->claims + G;
     a.wclaim = s->claims + 2 * G;
-    a.hdr = w.hdr + kHdrTicket;
     a.status = w.status;
+    a.acc = w.acc;
     a.blist[0] = w.list_a;
     a.blist[1] = w.list_b;
     a.d_nb[0] = reinterpret_cast<int64_t*>(w.hdr + kHdrCountA);
@@ -443,8 +455,12 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     const dim3 cell_grid(static_cast<uint32_t>(tiles_for(G, kBlock)));
     const dim3 agent_grid(static_cast<uint32_t>(tiles_for(p->cap_s + p->cap_w, kBlock)));
     const dim3 scan_grid(a.tiles[0] + a.tiles[1]);
-    // the claim tables must start the call empty whatever the caller did between calls
-    hipLaunchKernelGGL(k_regrow_rearm, cell_grid, dim3(kBlock), 0, st, s->grass, s->claims, G, 0);
+    // the claim tables and accumulators start the call empty whatever the
+    // caller did between calls
+    hipLaunchKernelGGL(k_regrow_rearm, cell_grid, dim3(kBlock), 0, st, s->grass, s->claims, G, 0,
+                       nullptr, nullptr);
+    hipLaunchKernelGGL(k_fill64, dim3(tiles_for(kAccWords, kBlock)), dim3(kBlock), 0, st, w.acc,
+                       kAccWords, int64_t(0));
     if (s->stats)
         hipLaunchKernelGGL(k_fill64, dim3(tiles_for(8 * int64_t(n_steps), kBlock)), dim3(kBlock),
                            0, st, s->stats, 8 * int64_t(n_steps), int64_t(0));
@@ -452,10 +468,14 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
         hipLaunchKernelGGL(k_move_claim, agent_grid, dim3(kBlock), 0, st, a);
+        rc = next_epoch(w, st, &a.epoch);
+        if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_eat_breeders, scan_grid, dim3(kWaves * 64), 0, st, a);
+        rc = next_epoch(w, st, &a.epoch);
+        if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_breed_die, scan_grid, dim3(kWaves * 64), 0, st, a);
         hipLaunchKernelGGL(k_regrow_rearm, cell_grid, dim3(kBlock), 0, st, s->grass, s->claims, G,
-                           1);
+                           1, w.acc, a.stats);
     }
     rc = launch_status("predation_step");
     if (rc == ABM_OK) s->step += uint32_t(n_steps);

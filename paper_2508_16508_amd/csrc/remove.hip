@@ -3,11 +3,9 @@
 //
 // Each lane owns 16 consecutive slots: one 16-byte load of the kill mask, and
 // only where some kill byte is set, 16-byte loads/stores of the matching alive
-// words (so a sparse kill mask touches only the alive lines it needs).  The
-// removed count is reduced per block and combined with one 64-bit atomic that
-// carries both a done-block counter (high half) and the running sum (low
-// half); the block that completes the count writes the result and re-arms the
-// word for the next call, so no clearing launch is needed.
+// words (so a sparse kill mask touches only the alive lines it needs).  Every
+// workgroup but the last publishes its removed count as an epoch-tagged status
+// word; the last one sums them (no same-address atomics, which serialise).
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -23,9 +21,10 @@ constexpr int64_t kSlotsPerBlock = int64_t(kBlock) * kSlotsPerLane;
 
 __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ kill,
                                                    int32_t* __restrict__ alive, int64_t n,
-                                                   uint64_t* acc, uint32_t nblocks,
+                                                   uint64_t* status, EpochArg ep,
                                                    int64_t* d_removed) {
     __shared__ uint32_t lds[kBlock / 64];
+    const uint32_t epoch = read_epoch(ep);
     const int64_t first = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kSlotsPerLane;
     uint32_t removed = 0;
     if (first + kSlotsPerLane <= n) {
@@ -59,17 +58,16 @@ __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ k
     const uint32_t wsum = wave_sum(removed);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = wsum;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t bsum = 0;
+    uint32_t bsum = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) bsum += lds[w];
-        const uint64_t old = __hip_atomic_fetch_add(acc, (uint64_t(1) << 32) | bsum,
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (uint32_t(old >> 32) == nblocks - 1) {
-            *d_removed = int64_t(uint32_t(old)) + bsum;
-            st_agent(acc, 0ull);
-        }
+    for (int w = 0; w < kBlock / 64; ++w) bsum += lds[w];
+    const uint32_t last = gridDim.x - 1;
+    if (blockIdx.x != last) {
+        if (threadIdx.x == 0) st_agent(&status[blockIdx.x], pack_status(epoch, kFlagAgg, bsum));
+        return;
     }
+    const uint32_t others = block_sum_published(status, last, epoch, status - 1, lds);
+    if (threadIdx.x == 0) *d_removed = int64_t(others) + bsum;
 }
 
 __global__ void k_zero_count(int64_t* d) {
@@ -103,7 +101,10 @@ extern "C" int abm_remove_agents(const abm_soa* dst, const uint8_t* kill_mask, i
         return launch_status("remove_agents");
     }
     const uint32_t nblocks = static_cast<uint32_t>(tiles_for(dst->capacity, kSlotsPerBlock));
+    EpochArg ep;
+    rc = next_epoch(w, st, &ep);
+    if (rc != ABM_OK) return rc;
     hipLaunchKernelGGL(k_remove, dim3(nblocks), dim3(kBlock), 0, st, kill_mask, dst->alive,
-                       dst->capacity, w.hdr + kHdrRemove, nblocks, d_removed);
+                       dst->capacity, w.status, ep, d_removed);
     return launch_status("remove_agents");
 }

@@ -6,16 +6,21 @@
 // This computes the paper's rank labels (Sec. 4, Alg. 1: cumulative sum of the
 // mask times the mask) in one O(n) pass, 0-based: rank(i) = #{i' < i selected}.
 //
-// Tile order.  Blocks take tile ids from an atomic ticket, so a tile only ever
-// waits on tiles that some running block already holds: forward progress does
-// not depend on the order in which the hardware dispatches workgroups.
+// Tile order.  Tile t is processed by workgroup t.  A tile only waits on tiles
+// with smaller ids, and each XCD dispatches its workgroups in increasing id
+// order, so the smallest unfinished tile always has its workgroup resident and
+// can finish.  (A ticket taken with one atomic per workgroup would not need
+// that property, but same-address atomics serialise at about 12 ns each on
+// MI355X: 4096 tiles would cost ~50 us.)  Waits are bounded: a wait that never
+// ends sets the workspace error word and counts the missing tile as zero, so
+// a broken assumption shows up as a reported error, never as a hung device.
 //
 // Status words.  One uint64 per tile: bits 63..34 epoch, 33..32 flag
 // (0 invalid, 1 aggregate, 2 inclusive prefix), 31..0 value.  The epoch is a
-// per-launch generation number kept next to the ticket, so status words from
-// earlier launches read as invalid and need no clearing pass.  Flag and value
-// share one word, so relaxed agent-scope atomics suffice: no payload is
-// published separately, and the 8 XCDs (separate L2s) see coherent values.
+// per-launch generation number, so status words left by earlier launches read
+// as invalid and need no clearing pass.  Flag and value share one word, so
+// relaxed agent-scope atomics suffice: no payload is published separately, and
+// the 8 XCDs (separate L2s) see coherent values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,18 +62,37 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Takes the next tile ticket (one thread per block).  The block that takes the
-// last ticket of the launch resets the counter and advances the epoch for the
-// next launch on this workspace; every other block has already taken its
-// ticket by then, and launches on one workspace are stream-ordered.
-__device__ __forceinline__ void take_ticket(uint64_t* hdr, uint32_t ntiles, uint32_t& tile,
-                                            uint32_t& epoch) {
-    const uint64_t old = __hip_atomic_fetch_add(hdr, 1ull, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    tile = static_cast<uint32_t>(old);
-    epoch = static_cast<uint32_t>(old >> 32) & kEpochMask;
-    if (tile == ntiles - 1)
-        st_agent(hdr, static_cast<uint64_t>((epoch + 1) & kEpochMask) << 32);
+// Epoch of a launch: a host-chosen value passed as an argument, or, for
+// launches recorded into a graph (whose arguments are frozen), a device word
+// that a one-thread kernel advances before each such launch.
+struct EpochArg {
+    uint32_t value;
+    const uint32_t* dev;
+};
+
+__device__ __forceinline__ uint32_t read_epoch(const EpochArg& e) {
+    return (e.dev ? __hip_atomic_load(e.dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : e.value) &
+           kEpochMask;
+}
+
+__device__ __forceinline__ bool status_valid(uint64_t w, uint32_t epoch) {
+    const uint32_t hi = static_cast<uint32_t>(w >> 32);
+    return (hi >> 2) == epoch && (hi & 3u) != 0u;
+}
+
+// Polls one status word until it carries this launch's epoch (bounded).
+__device__ __forceinline__ uint64_t poll_status(const uint64_t* p, uint64_t w, uint32_t epoch,
+                                                uint64_t* err) {
+    uint32_t spins = 0;
+    while (!status_valid(w, epoch)) {
+        if (++spins > kSpinLimit) {
+            st_agent(err, 1ull);
+            return pack_status(epoch, kFlagPfx, 0u);
+        }
+        __builtin_amdgcn_s_sleep(1);
+        w = ld_agent(p);
+    }
+    return w;
 }
 
 // Decoupled look-back, run by one whole wave.  Publishes this tile's aggregate,
@@ -90,19 +114,7 @@ __device__ __forceinline__ uint32_t lookback(uint64_t* status, uint64_t* err, ui
         const int64_t idx = pos - lane;
         uint32_t flag = kFlagPfx, value = 0;
         if (idx >= static_cast<int64_t>(seg_first)) {
-            uint64_t w;
-            uint32_t spins = 0;
-            for (;;) {
-                w = ld_agent(&status[idx]);
-                const uint32_t hi = static_cast<uint32_t>(w >> 32);
-                if ((hi >> 2) == epoch && (hi & 3u) != 0u) break;
-                if (++spins > kSpinLimit) {
-                    st_agent(err, 1ull);
-                    w = pack_status(epoch, kFlagPfx, 0u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
+            const uint64_t w = poll_status(&status[idx], ld_agent(&status[idx]), epoch, err);
             flag = static_cast<uint32_t>(w >> 32) & 3u;
             value = static_cast<uint32_t>(w);
         }
@@ -197,6 +209,38 @@ __device__ __forceinline__ uint32_t rank_counts(uint32_t c, uint32_t* thread_exc
     *thread_excl = wave_excl + excl;
     *tile_total = total;
     return lds[WAVES];
+}
+
+// Sum of the values published (with this epoch) by status[0 .. count), read
+// by the whole block with many polls in flight; the result is valid in every
+// thread.  Used by reductions whose last workgroup produces the total, so the
+// other workgroups never wait.  lds holds blockDim / 64 words.
+__device__ __forceinline__ uint32_t block_sum_published(const uint64_t* status, int64_t count,
+                                                        uint32_t epoch, uint64_t* err,
+                                                        uint32_t* lds) {
+    constexpr int kBatch = 8;
+    uint32_t acc = 0;
+    for (int64_t base = 0; base < count; base += int64_t(kBatch) * blockDim.x) {
+        uint64_t w[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int64_t i = base + int64_t(k) * blockDim.x + threadIdx.x;
+            w[k] = i < count ? ld_agent(&status[i]) : pack_status(epoch, kFlagAgg, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int64_t i = base + int64_t(k) * blockDim.x + threadIdx.x;
+            if (i < count) w[k] = poll_status(&status[i], w[k], epoch, err);
+            acc += static_cast<uint32_t>(w[k]);
+        }
+    }
+    acc = wave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    uint32_t total = 0;
+    for (int i = 0; i < int(blockDim.x >> 6); ++i) total += lds[i];
+    return total;
 }
 
 }  // namespace abm

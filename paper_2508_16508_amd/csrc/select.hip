@@ -36,8 +36,8 @@ struct SelArgs {
     int64_t n;                // slots
     int64_t* d_applied;       // placed records (compact: number selected)
     int64_t* d_dropped;
-    uint64_t* hdr;
     uint64_t* status;
+    EpochArg epoch;
     uint32_t ntiles;
     int32_t n_attrs;
     int32_t vec_ok;           // mask / alive allow 16-byte loads
@@ -90,16 +90,9 @@ __device__ __forceinline__ uint32_t load_bits(const SelArgs& a, int64_t first) {
 template <int MODE, int NA>
 __global__ __launch_bounds__(kBlock) void k_select(SelArgs a) {
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ uint32_t s_tile, s_epoch;
     __shared__ uint16_t pos[kTile];
-    if (threadIdx.x == 0) {
-        uint32_t t, e;
-        take_ticket(a.hdr, a.ntiles, t, e);
-        s_tile = t;
-        s_epoch = e;
-    }
-    __syncthreads();
-    const uint32_t tile = s_tile, epoch = s_epoch;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t epoch = read_epoch(a.epoch);
     const int64_t tbase = int64_t(tile) * kTile;
     uint32_t bits = load_bits<MODE>(a, tbase + int64_t(threadIdx.x) * kSlotsPerLane);
 
@@ -228,8 +221,9 @@ int launch_compact(const uint8_t* mask, int64_t n, int32_t* out, int64_t* d_coun
     c.out_idx = out;
     c.d_applied = d_count;
     c.n = n;
-    c.hdr = w.hdr + kHdrTicket;
     c.status = w.status;
+    int rc = next_epoch(w, st, &c.epoch);
+    if (rc != ABM_OK) return rc;
     c.ntiles = static_cast<uint32_t>(tiles_for(n, kTile));
     c.vec_ok = aligned16(mask);
     hipLaunchKernelGGL((k_select<kCompact, 1>), dim3(c.ntiles), dim3(kBlock), 0, st, c);
@@ -281,10 +275,11 @@ extern "C" int abm_select_update(const abm_soa* dst, const uint8_t* sel_mask,
     a.n = dst->capacity;
     a.d_applied = d_applied;
     a.d_dropped = d_dropped;
-    a.hdr = w.hdr + kHdrTicket;
     a.status = w.status;
     a.ntiles = static_cast<uint32_t>(tiles_for(dst->capacity, kTile));
     a.vec_ok = aligned16(sel_mask);
+    rc = next_epoch(w, st, &a.epoch);
+    if (rc != ABM_OK) return rc;
     if (d_q)
         launch_select<kSelIndirect>(a, st);
     else
@@ -317,10 +312,11 @@ extern "C" int abm_add_agents(const abm_soa* dst, const abm_records* newborn, in
     a.n = dst->capacity;
     a.d_applied = d_added;
     a.d_dropped = d_dropped;
-    a.hdr = w.hdr + kHdrTicket;
     a.status = w.status;
     a.ntiles = static_cast<uint32_t>(tiles_for(dst->capacity, kTile));
     a.vec_ok = aligned16(dst->alive);
+    rc = next_epoch(w, st, &a.epoch);
+    if (rc != ABM_OK) return rc;
     launch_select<kAddDense>(a, st);
     return launch_status("add_agents");
 }

@@ -53,6 +53,7 @@ def test_small_workload_every_step(abm, orc, seed):
         got = dict(zip(abm.STAT_NAMES, (int(v) for v in _host(stats)[0])))
         assert got == exp, f"stats step {t}"
         _assert_same(model, S, f"after step {t}")
+    assert abm.workspace_error(model.ws) == 0
 
 
 @pytest.mark.parametrize("W,H,cap_s,cap_w,n_s0,n_w0", [
@@ -124,3 +125,4 @@ def test_large_workload(abm, orc):
         assert ge <= P.W * P.H and se <= live_s
     alive_s = int(_host(model.sheep["alive"]).sum())
     assert alive_s == st[n - 1][0] - st[n - 1][3] - st[n - 1][6] + st[n - 1][4]
+    assert abm.workspace_error(model.ws) == 0

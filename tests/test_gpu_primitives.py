@@ -77,6 +77,7 @@ def test_shared_workspace_across_calls_of_varying_size(abm, orc):
         got, ga, gd = _run_select(abm, attrs, mask, recs, ws=ws)
         assert (ga, gd) == (ea, ed), (it, n)
         assert np.array_equal(got, exp), (it, n)
+    assert abm.workspace_error(ws) == 0
 
 
 def test_select_update_idempotent_and_deterministic(abm):
@@ -166,6 +167,7 @@ def test_remove_agents_repeated_calls_share_counter(abm, orc):
         removed = abm.remove_agents(d_alive, dev(kill), ws=ws)
         assert int(host(removed)[0]) == er, (it, n)
         assert np.array_equal(host(d_alive), exp)
+    assert abm.workspace_error(ws) == 0
 
 
 @pytest.mark.parametrize("n", SIZES)
@@ -209,3 +211,50 @@ def test_resolve_conflicts_full_priority_range(abm, orc):
     assert np.array_equal(host(best), eb)
     assert np.array_equal(host(winner), ew)
     assert np.array_equal(host(won), ewon)
+
+
+def test_graph_replay_select_add_remove(abm, orc):
+    """select_update, add_agents and remove_agents recorded once into a graph and
+    replayed with fresh inputs copied in between: the device-side epoch keeps
+    every replay's scan separate from the last one's."""
+    n, A, k = 200_000, 4, 30_000
+    ws = abm.workspace(n)
+    cnt = torch.zeros(8, dtype=torch.int64, device="cuda")
+    d_attrs = torch.zeros((A, n), dtype=torch.int32, device="cuda")
+    d_mask = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    d_recs = torch.zeros((A, k), dtype=torch.int32, device="cuda")
+    d_alive = torch.ones(n, dtype=torch.int32, device="cuda")
+    d_kill = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        # warm-up outside capture (library load, device check)
+        abm.select_update(d_attrs, d_mask, d_recs, ws=ws, applied=cnt[0:1], dropped=cnt[1:2])
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        abm.select_update(d_attrs, d_mask, d_recs, ws=ws, applied=cnt[0:1], dropped=cnt[1:2])
+        abm.add_agents(d_attrs, d_alive, d_recs, ws=ws, added=cnt[2:3], dropped=cnt[3:4])
+        abm.remove_agents(d_alive, d_kill, ws=ws, removed=cnt[4:5])
+    for it in range(6):
+        attrs = W.int32_rows(100 + it, A, n)
+        mask = W.bernoulli_mask(200 + it, 0.1 + 0.1 * it, n)
+        recs = W.int32_rows(300 + it, A, k)
+        alive = (1 - W.bernoulli_mask(400 + it, 0.2, n)).astype(np.int32)
+        kill = W.bernoulli_mask(500 + it, 0.3, n)
+        d_attrs.copy_(dev(attrs))
+        d_mask.copy_(dev(mask))
+        d_recs.copy_(dev(recs))
+        d_alive.copy_(dev(alive))
+        d_kill.copy_(dev(kill))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        e1, ea, ed = orc.select_update(attrs, mask, recs)
+        e2, eal, eadd, edrop = orc.add_agents(e1, alive, recs)
+        eal2, erem = orc.remove_agents(eal, kill)
+        c = host(cnt)
+        assert (c[0], c[1], c[2], c[3], c[4]) == (ea, ed, eadd, edrop, erem), it
+        assert np.array_equal(host(d_attrs), e2), it
+        assert np.array_equal(host(d_alive), eal2), it
+    assert abm.workspace_error(ws) == 0
