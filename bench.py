@@ -92,6 +92,73 @@ def cpu_baseline(sample_seconds):
                       f"via its ctypes wrapper ({dt:.1f} s)"}
 
 
+def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps=20):
+    """Batched form: 4096 uneven predation models (side 32-256, sheep = cells/10,
+    wolves = cells/40, capacities 4x), `steps` steps as a graph of persistent
+    launches of `chunk` steps each, against the one-model multi-launch path
+    timed on a stratified subset of the same models (rates in agent updates/s;
+    both paths compute bit-identical states)."""
+    specs = W.batched_models(0, 4096)
+    params = [abm.predation_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s,
+                                   cap_w=sp.cap_w, n_s0=sp.n_s0, n_w0=sp.n_w0) for sp in specs]
+    batch = abm.BatchedPredation(params, steps)
+    batch.init()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        batch.run(1, stream=side)          # warm-up (first step of every model)
+    side.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(0, steps - 1, chunk):
+            batch.run(chunk, stream=side)
+    torch.cuda.synchronize()
+    d0 = batch.descriptors()
+    u0 = sum(d.updates for d in d0)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d1 = batch.descriptors()
+    assert all(d.step == steps for d in d1)
+    updates = sum(d.updates for d in d1) - u0
+    cells = sum(sp.side * sp.side for sp in specs)
+    del batch, graph
+    torch.cuda.empty_cache()
+
+    # one-model path on a stratified subset (every 128th model by size)
+    by_size = sorted(range(len(specs)), key=lambda m: specs[m].side)
+    pick = by_size[:: max(1, len(specs) // plain_models)][:plain_models]
+    models = [abm.predation_init(params[m]) for m in pick]
+    stats = [torch.zeros((plain_steps, 8), dtype=torch.int64, device="cuda") for _ in pick]
+    for mdl in models:
+        mdl.run(1)                          # warm-up
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record()
+    for mdl, st in zip(models, stats):
+        mdl.run(plain_steps, st)
+    p1.record()
+    torch.cuda.synchronize()
+    pms = p0.elapsed_time(p1)
+    pupd = sum(int(st[:, 0].sum().item() + st[:, 1].sum().item()) for st in stats)
+    rate_b = updates / (ms / 1e3)
+    rate_p = pupd / (pms / 1e3)
+    return {"workload": "4096 predation models, side uniform in [32, 256], sheep = cells/10, "
+                        "wolves = cells/40, capacities 4x, seeds base+m; "
+                        f"{steps - 1} timed steps as one graph of {chunk}-step persistent launches",
+            "cells": cells, "agent_updates": updates, "ms": ms,
+            "agent_updates_per_s": rate_b,
+            "plain_agent_updates_per_s": rate_p,
+            "plain_sample": f"{len(pick)} models (every {len(specs) // plain_models}th by size), "
+                            f"{plain_steps} steps each, one-model multi-launch path",
+            "batched_over_plain": rate_b / rate_p}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +167,7 @@ def main():
     ap.add_argument("--sets", type=int, default=10, help="rotated input sets (seeds 0..sets-1)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -149,7 +217,7 @@ def main():
                     abm.remove_agents(d["alive"], d["mask"], ws=ws, removed=cnt[4:5])
                 if timed:
                     e1.record(stream)
-                    events[op].append((e0, e1, d["k"]))
+                    events[op].append((e0, e1, d["k"], d["p"]))
 
     for s in range(args.warmup):
         step(s, False)
@@ -179,12 +247,18 @@ def main():
 
     kernels = {}
     for op in ops:
-        durs = [e0.elapsed_time(e1) * 1e-3 for e0, e1, _ in events[op]]
-        byts = [algorithmic_bytes(op, N_SLOTS, k) for _, _, k in events[op]]
+        durs = [e0.elapsed_time(e1) * 1e-3 for e0, e1, _, _ in events[op]]
+        byts = [algorithmic_bytes(op, N_SLOTS, k) for _, _, k, _ in events[op]]
         mean_s = float(np.mean(durs))
+        by_p = {}
+        for p in W.DENSITIES:
+            dp = [e0.elapsed_time(e1) * 1e-3 for e0, e1, _, pp in events[op] if pp == p]
+            bp = [algorithmic_bytes(op, N_SLOTS, k) for _, _, k, pp in events[op] if pp == p]
+            by_p[str(p)] = dict(mean_us=float(np.mean(dp)) * 1e6,
+                                gbs=float(np.mean(bp)) / float(np.mean(dp)) / 1e9)
         kernels[op] = dict(launches=len(durs), mean_us=mean_s * 1e6, total_ms=sum(durs) * 1e3,
                            bytes_per_launch=float(np.mean(byts)),
-                           gbs=float(np.mean(byts)) / mean_s / 1e9)
+                           gbs=float(np.mean(byts)) / mean_s / 1e9, by_density=by_p)
     dom = max(ops, key=lambda o: kernels[o]["total_ms"])
     kd = kernels[dom]
     src_hash = kernel_sources_hash()
@@ -208,9 +282,11 @@ def main():
         "kernels": kernels,
         "kernel_sources": src_hash,
     }
+    del sets, dst
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_leg(abm, W, torch)
     if not args.no_cpu_baseline:
-        del sets, dst
-        torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -217,6 +217,69 @@ ABM_API int abm_predation_init(const abm_predation_params* p, abm_predation_stat
 ABM_API int abm_predation_step(const abm_predation_params* p, abm_predation_state* s, int32_t n_steps,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched predation: many independent models of uneven sizes advanced by one
+ * persistent launch (the paper vectorises identical models, Sec. 2 and
+ * Table 2; here shapes may differ).  Every model follows exactly the one-model
+ * definition above with its own parameters and seed, so each model's state
+ * is bit-identical to running it alone.
+ *
+ * Packed layout: model m owns cells [cell_off, cell_off + W*H) of `ready`
+ * (one int32 per cell) and of `claims` (three uint64 per cell), and slots
+ * [sheep_off, sheep_off + cap_s) / [wolf_off, wolf_off + cap_w) of the species
+ * arrays.  Ranges must not overlap.  `ready` holds the step at which a cell is
+ * grown again (grown at step t iff ready <= t); abm_predation_batched_grass
+ * converts it to the countdown form of abm_predation_state.
+ * ------------------------------------------------------------------------- */
+typedef struct abm_model_desc {   /* device array; the library updates the last five fields */
+    int32_t W, H, R, gain_s, gain_w;
+    uint32_t T_s, T_w, seed;
+    int64_t cap_s, cap_w;          /* each in [1, 2^30] */
+    int64_t n_s0, n_w0;
+    int64_t cell_off, sheep_off, wolf_off;
+    int32_t step;                  /* steps done so far (0 after init) */
+    int32_t steps_target;          /* a run stops advancing the model here */
+    int64_t updates;               /* sum over steps run of live agents at step start */
+    int64_t live_s, live_w;        /* live agents after the last run */
+} abm_model_desc;
+
+typedef struct abm_batch {        /* host struct of device pointers */
+    int32_t n_models;              /* 0 .. 65535 */
+    int64_t max_cap;               /* max over models of max(cap_s, cap_w) */
+    abm_model_desc* models;        /* device abm_model_desc[n_models] */
+    int32_t* ready;                /* device int32[sum of W*H] */
+    uint64_t* claims;              /* device uint64[3 * sum of W*H]; set by init, kept all-ones between runs */
+    abm_species sheep, wolves;     /* device int32[sum of caps] each */
+} abm_batch;
+
+typedef struct abm_tuning {
+    int32_t block_threads;         /* threads per model workgroup (multiple of 64 in [256, 1024]); 0 = 512 */
+    int32_t workgroups;            /* persistent workgroups; 0 = as many as are resident at once */
+    int32_t items;                 /* slots per thread per chunk: 1, 2, 4 or 8; 0 = 4 */
+} abm_tuning;
+
+/* Workspace for abm_predation_run_batched: a breeder list per workgroup.  Its
+ * 256-byte header ends with an error word (offset 248) that a run sets to 1
+ * if some descriptor's cap_s + cap_w exceeds 2 * max_cap (that model is then
+ * left untouched). */
+ABM_API size_t abm_batched_workspace_bytes(int64_t max_cap, int32_t n_workgroups);
+
+/* Initial state of every model (the one-model definition per model, with the
+ * model's seed); descriptors must hold step = 0 and updates = 0. */
+ABM_API int abm_predation_batched_init(const abm_batch* b, void* stream);
+
+/* Advance every model by min(max_steps, steps_target - step) steps.  order is
+ * a device int32 permutation of [0, n_models): workgroups take models in that
+ * order (largest first balances the load).  Afterwards each descriptor's
+ * step, updates, live_s and live_w are current. */
+ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, int32_t max_steps,
+                                      const abm_tuning* tune, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* countdown[cell_off + c] = max(0, ready[cell_off + c] - step) for every model:
+ * the grass array of the one-model state.  countdown: device int32[sum of W*H]. */
+ABM_API int abm_predation_batched_grass(const abm_batch* b, int32_t* countdown, void* stream);
+
 /* Message describing the last non-OK status returned on this thread. */
 ABM_API const char* abm_last_error(void);
 

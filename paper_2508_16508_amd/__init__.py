@@ -26,7 +26,8 @@ ABM_OP_SELECT_INDICES, ABM_OP_PREDATION = 4, 5
 EXPORTED = (
     "abm_workspace_bytes", "abm_workspace_init", "abm_select_update", "abm_select_indices",
     "abm_add_agents", "abm_remove_agents", "abm_resolve_conflicts", "abm_predation_init",
-    "abm_predation_step", "abm_last_error", "abm_version",
+    "abm_predation_step", "abm_last_error", "abm_version", "abm_batched_workspace_bytes",
+    "abm_predation_batched_init", "abm_predation_run_batched", "abm_predation_batched_grass",
 )
 
 
@@ -63,6 +64,16 @@ class PredationStatePtrs(C.Structure):
                 ("claims", C.c_void_p), ("stats", C.c_void_p), ("step", C.c_uint32)]
 
 
+class Batch(C.Structure):
+    _fields_ = [("n_models", C.c_int32), ("max_cap", C.c_int64), ("models", C.c_void_p),
+                ("ready", C.c_void_p), ("claims", C.c_void_p), ("sheep", SpeciesPtrs),
+                ("wolves", SpeciesPtrs)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("workgroups", C.c_int32), ("items", C.c_int32)]
+
+
 _lib = None
 
 
@@ -88,10 +99,17 @@ def lib():
                                          C.POINTER(PredationStatePtrs), vp]
         L.abm_predation_step.argtypes = [C.POINTER(PredationParams),
                                          C.POINTER(PredationStatePtrs), i32, vp, sz, vp]
+        L.abm_batched_workspace_bytes.argtypes = [i64, i32]
+        L.abm_batched_workspace_bytes.restype = sz
+        L.abm_predation_batched_init.argtypes = [C.POINTER(Batch), vp]
+        L.abm_predation_run_batched.argtypes = [C.POINTER(Batch), vp, i32, C.POINTER(Tuning), vp,
+                                                sz, vp]
+        L.abm_predation_batched_grass.argtypes = [C.POINTER(Batch), vp, vp]
         L.abm_last_error.restype = C.c_char_p
         L.abm_version.restype = C.c_char_p
         for name in EXPORTED:
-            if name not in ("abm_workspace_bytes", "abm_last_error", "abm_version"):
+            if name not in ("abm_workspace_bytes", "abm_last_error", "abm_version",
+                            "abm_batched_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -328,3 +346,100 @@ def predation_step(model: PredationModel, n_steps: int = 1, stats=None, stream=N
 
 STAT_NAMES = ("live_s", "live_w", "grass_eaten", "sheep_eaten", "births_s", "births_w",
               "starved_s", "starved_w")
+
+
+# ---------------------------------------------------------------- batched predation
+
+class ModelDesc(C.Structure):
+    """Mirror of abm_model_desc."""
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("R", C.c_int32),
+                ("gain_s", C.c_int32), ("gain_w", C.c_int32),
+                ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
+                ("cap_s", C.c_int64), ("cap_w", C.c_int64),
+                ("n_s0", C.c_int64), ("n_w0", C.c_int64),
+                ("cell_off", C.c_int64), ("sheep_off", C.c_int64), ("wolf_off", C.c_int64),
+                ("step", C.c_int32), ("steps_target", C.c_int32),
+                ("updates", C.c_int64), ("live_s", C.c_int64), ("live_w", C.c_int64)]
+
+
+class BatchedPredation:
+    """Many predation models of uneven sizes, packed for one persistent launch.
+
+    models: list of PredationParams (one per model); steps_target: per model
+    (int or list).  Slot and cell ranges are packed in model order; the launch
+    order is largest model first."""
+
+    def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4):
+        self.params = list(models)
+        n = len(self.params)
+        tgt = [steps_target] * n if isinstance(steps_target, int) else list(steps_target)
+        self.n_models = n
+        descs = (ModelDesc * max(1, n))()
+        g_off = s_off = w_off = 0
+        for m, p in enumerate(self.params):
+            d = descs[m]
+            for f in ("W", "H", "R", "gain_s", "gain_w", "T_s", "T_w", "seed", "cap_s", "cap_w",
+                      "n_s0", "n_w0"):
+                setattr(d, f, getattr(p, f))
+            d.cell_off, d.sheep_off, d.wolf_off = g_off, s_off, w_off
+            d.step, d.steps_target = 0, int(tgt[m])
+            g_off += p.W * p.H
+            s_off += p.cap_s
+            w_off += p.cap_w
+        self.cells, self.slots_s, self.slots_w = g_off, s_off, w_off
+        self.max_cap = max([max(p.cap_s, p.cap_w) for p in self.params] or [1])
+        z = lambda k: torch.zeros(max(1, k), dtype=torch.int32, device=device)
+        self.ready = z(g_off)
+        self.claims = torch.empty(3 * max(1, g_off), dtype=torch.uint64, device=device)
+        self.sheep = {f: z(s_off) for f in ("x", "y", "e", "alive")}
+        self.wolves = {f: z(w_off) for f in ("x", "y", "e", "alive")}
+        raw = bytes(descs)
+        self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        size = [p.W * p.H + p.cap_s + p.cap_w for p in self.params]
+        order = sorted(range(n), key=lambda m: -size[m])
+        self.order = torch.tensor(order or [0], dtype=torch.int32, device=device)
+        self.block_threads = block_threads
+        self.items = items
+        props = torch.cuda.get_device_properties(self.ready.device)
+        self.workgroups = props.multi_processor_count * max(1, 2048 // block_threads)
+        nbytes = int(lib().abm_batched_workspace_bytes(self.max_cap, self.workgroups))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off: off + nbytes]
+
+    def _batch(self) -> Batch:
+        sp = lambda d: SpeciesPtrs(*(d[k].data_ptr() for k in ("x", "y", "e", "alive")))
+        return Batch(self.n_models, self.max_cap, self.desc.data_ptr(), self.ready.data_ptr(),
+                     self.claims.data_ptr(), sp(self.sheep), sp(self.wolves))
+
+    def init(self, stream=None):
+        b = self._batch()
+        _check(lib().abm_predation_batched_init(C.byref(b), _stream(stream)))
+
+    def run(self, max_steps: int, stream=None, block_threads=None, workgroups=None, items=None):
+        b = self._batch()
+        t = Tuning(block_threads or self.block_threads, workgroups or self.workgroups,
+                   items or self.items)
+        _check(lib().abm_predation_run_batched(C.byref(b), _p(self.order), max_steps, C.byref(t),
+                                               _p(self.ws), self.ws.numel(), _stream(stream)))
+
+    def descriptors(self):
+        """Host copy of the model descriptors (synchronises)."""
+        raw = self.desc.cpu().numpy().tobytes()
+        return (ModelDesc * max(1, self.n_models)).from_buffer_copy(raw)[: self.n_models]
+
+    def grass_countdown(self, stream=None) -> torch.Tensor:
+        out = torch.zeros(max(1, self.cells), dtype=torch.int32, device=self.ready.device)
+        b = self._batch()
+        _check(lib().abm_predation_batched_grass(C.byref(b), _p(out), _stream(stream)))
+        return out
+
+    def model_state(self, m: int, countdown: torch.Tensor | None = None):
+        """(grass countdown, sheep dict, wolves dict) of model m as device views."""
+        p = self.params[m]
+        dm = self.descriptors()[m]
+        g = countdown if countdown is not None else self.grass_countdown()
+        grass = g[dm.cell_off: dm.cell_off + p.W * p.H]
+        sheep = {k: v[dm.sheep_off: dm.sheep_off + p.cap_s] for k, v in self.sheep.items()}
+        wolves = {k: v[dm.wolf_off: dm.wolf_off + p.cap_w] for k, v in self.wolves.items()}
+        return grass, sheep, wolves

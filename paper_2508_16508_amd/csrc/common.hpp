@@ -58,7 +58,12 @@ enum HeaderWord : int {
 
 inline int64_t tiles_for(int64_t n, int64_t tile) { return (n + tile - 1) / tile; }
 
-inline int64_t status_words(int64_t capacity) { return 2 * tiles_for(capacity, kMinTile) + 2; }
+// Room for two scan chains of ceil(C / kMinTile) tiles each plus their group
+// words (a chain of T tiles needs less than T + T/63 + 4 words).
+inline int64_t status_words(int64_t capacity) {
+    const int64_t t = tiles_for(capacity, kMinTile);
+    return 2 * (t + t / 63 + 8) + 2;
+}
 
 inline size_t workspace_bytes(int64_t capacity) {
     if (capacity < 1) capacity = 1;

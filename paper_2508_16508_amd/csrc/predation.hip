@@ -69,6 +69,7 @@ struct StepArgs {
     int32_t* blist[2];    // breeder lists
     int64_t* d_nb[2];     // breeder counts
     uint32_t tiles[2];
+    uint32_t chain_off[2];  // start of each species' scan chain in the status words
 };
 
 __device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t n) {
@@ -246,7 +247,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
     }
     uint32_t rank[kItems], total;
     const uint32_t tile_excl =
-        rank_tile<kWaves, kItems>(f, rank, a.status, tile, seg_first, epoch, lds, &total);
+        rank_tile<kWaves, kItems>(f, rank, a.status + a.chain_off[s], a.status - 1,
+                                  tile - seg_first, a.tiles[s], epoch, lds, &total);
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
         if (f[k]) a.blist[s][rank[k]] = int32_t(base + k * 64);
@@ -280,7 +282,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_breed_die(StepArgs a) {
     }
     uint32_t rank[kItems], total;
     const uint32_t tile_excl =
-        rank_tile<kWaves, kItems>(f, rank, a.status, tile, seg_first, epoch, lds, &total);
+        rank_tile<kWaves, kItems>(f, rank, a.status + a.chain_off[s], a.status - 1,
+                                  tile - seg_first, a.tiles[s], epoch, lds, &total);
     const int64_t nb = *a.d_nb[s];
     uint32_t starved = 0;
 #pragma unroll
@@ -451,6 +454,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.d_nb[1] = reinterpret_cast<int64_t*>(w.hdr + kHdrCountB);
     a.tiles[0] = static_cast<uint32_t>(tiles_for(p->cap_s, kTile));
     a.tiles[1] = static_cast<uint32_t>(tiles_for(p->cap_w, kTile));
+    a.chain_off[0] = 0;
+    a.chain_off[1] = static_cast<uint32_t>(chain_words(a.tiles[0]));
 
     const dim3 cell_grid(static_cast<uint32_t>(tiles_for(G, kBlock)));
     const dim3 agent_grid(static_cast<uint32_t>(tiles_for(p->cap_s + p->cap_w, kBlock)));

@@ -1,9 +1,12 @@
 // remove.hip -- abm_remove_agents: the paper's set_agents_mask (Sec. 2), an
 // independent masked update with no ranking: alive[i] = 0 wherever kill[i].
 //
-// Each lane owns 16 consecutive slots: one 16-byte load of the kill mask, and
-// only where some kill byte is set, 16-byte loads/stores of the matching alive
-// words (so a sparse kill mask touches only the alive lines it needs).  Every
+// Each lane owns 32 consecutive slots: two 16-byte loads of the kill mask,
+// then, only for the 16-byte alive chunks holding a set kill byte, 16-byte
+// loads and stores of alive (a sparse kill mask touches only the alive lines
+// it needs).  The conditional accesses are buffer instructions whose offset is
+// moved out of range when not wanted -- the hardware then skips the access --
+// so there are no branches and all eight loads are in flight together.  Every
 // workgroup but the last publishes its removed count as an epoch-tagged status
 // word; the last one sums them (no same-address atomics, which serialise).
 #include <hip/hip_runtime.h>
@@ -16,7 +19,8 @@ namespace abm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSlotsPerLane = 16;
+constexpr int kSlotsPerLane = 32;
+constexpr int kSkip = int(0x80000000u);   // out-of-range buffer offset: access skipped
 constexpr int64_t kSlotsPerBlock = int64_t(kBlock) * kSlotsPerLane;
 
 __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ kill,
@@ -28,24 +32,31 @@ __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ k
     const int64_t first = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kSlotsPerLane;
     uint32_t removed = 0;
     if (first + kSlotsPerLane <= n) {
-        const uint4 km = *reinterpret_cast<const uint4*>(kill + first);
-        const uint32_t kw[4] = {km.x, km.y, km.z, km.w};
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const int64_t bfirst = int64_t(blockIdx.x) * kSlotsPerBlock;
+        const int64_t bn = (n - bfirst) < kSlotsPerBlock ? (n - bfirst) : kSlotsPerBlock;
+        const __amdgpu_buffer_rsrc_t ra =
+            __builtin_amdgcn_make_buffer_rsrc(alive + bfirst, 0, int(bn * 4), 0x00020000);
+        const uint4* kp = reinterpret_cast<const uint4*>(kill + first);
+        const uint4 k0 = kp[0], k1 = kp[1];
+        const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+        const int lo = int(threadIdx.x) * kSlotsPerLane * 4;
+        v4i al[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (kw[q] == 0u) continue;
-            int4* ap = reinterpret_cast<int4*>(alive + first + 4 * q);
-            int4 al = *ap;
-            int32_t v[4] = {al.x, al.y, al.z, al.w};
+        for (int q = 0; q < 8; ++q)
+            al[q] = __builtin_amdgcn_raw_buffer_load_b128(ra, kw[q] ? lo + 16 * q : kSkip, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
             bool changed = false;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                if (((kw[q] >> (8 * b)) & 0xFFu) != 0u && v[b] != 0) {
+                if (((kw[q] >> (8 * b)) & 0xFFu) != 0u && al[q][b] != 0) {
                     ++removed;
-                    v[b] = 0;
+                    al[q][b] = 0;
                     changed = true;
                 }
             }
-            if (changed) *ap = make_int4(v[0], v[1], v[2], v[3]);
+            __builtin_amdgcn_raw_buffer_store_b128(al[q], ra, changed ? lo + 16 * q : kSkip, 0, 0);
         }
     } else {
         for (int64_t s = first; s < n && s < first + kSlotsPerLane; ++s) {

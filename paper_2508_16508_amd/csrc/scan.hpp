@@ -1,7 +1,7 @@
 // scan.hpp -- single-pass exclusive prefix count over a selection mask:
-// wave ballot/mbcnt ranks, an LDS scan of wave totals, and decoupled
-// look-back across tiles (Merrill & Garland, "Single-pass Parallel Prefix Scan
-// with Decoupled Look-back", 2016).
+// wave ballot/mbcnt ranks, an LDS scan of wave totals, and a hierarchical
+// look-back across tiles (after the decoupled look-back of Merrill & Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).
 //
 // This computes the paper's rank labels (Sec. 4, Alg. 1: cumulative sum of the
 // mask times the mask) in one O(n) pass, 0-based: rank(i) = #{i' < i selected}.
@@ -15,12 +15,22 @@
 // ends sets the workspace error word and counts the missing tile as zero, so
 // a broken assumption shows up as a reported error, never as a hung device.
 //
-// Status words.  One uint64 per tile: bits 63..34 epoch, 33..32 flag
-// (0 invalid, 1 aggregate, 2 inclusive prefix), 31..0 value.  The epoch is a
-// per-launch generation number, so status words left by earlier launches read
-// as invalid and need no clearing pass.  Flag and value share one word, so
-// relaxed agent-scope atomics suffice: no payload is published separately, and
-// the 8 XCDs (separate L2s) see coherent values.
+// Hierarchy.  With ~2000 tiles resident at once, a flat look-back either polls
+// O(T^2) status words in total or waits O(T / window) device round trips for
+// the prefix frontier to arrive.  Instead tiles form groups of 64, groups form
+// groups of 64, and so on.  Every tile publishes its own count (level 0); the
+// last tile of each level-l group publishes the group's total at level l+1 as
+// soon as it has summed that group's members, which depend only on lower
+// levels -- never on earlier groups -- so no chain forms.  A tile's exclusive
+// prefix is then, per level, the sum of at most 63 earlier siblings: one wave
+// per level polls them in parallel (about two device round trips in total for
+// 4096 tiles, and little polling traffic).
+//
+// Status words.  One uint64 per word: bits 63..34 epoch, 33..32 flag (1 =
+// valid), 31..0 value.  The epoch is a per-launch generation number, so words
+// left by earlier launches read as invalid and need no clearing pass.  Flag
+// and value share one word, so relaxed agent-scope atomics suffice: no payload
+// is published separately, and the 8 XCDs (separate L2s) see coherent values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -95,38 +105,66 @@ __device__ __forceinline__ uint64_t poll_status(const uint64_t* p, uint64_t w, u
     return w;
 }
 
-// Decoupled look-back, run by one whole wave.  Publishes this tile's aggregate,
-// accumulates predecessors back to the nearest inclusive prefix (or to the
-// first tile of the segment, which counts as prefix 0), publishes this tile's
-// inclusive prefix and returns the exclusive prefix.
-__device__ __forceinline__ uint32_t lookback(uint64_t* status, uint64_t* err, uint32_t tile,
-                                             uint32_t seg_first, uint32_t epoch,
-                                             uint32_t aggregate) {
+// Number of status words one scan chain (segment) of T tiles uses: the tile
+// words followed by each level's group words.
+constexpr int kLevels = 4;  // 64^4 tiles per chain
+
+__host__ __device__ __forceinline__ int64_t chain_words(int64_t T) {
+    int64_t words = 0, n = T;
+    for (int l = 0; l < kLevels; ++l) {
+        words += n;
+        n = (n + 63) >> 6;
+    }
+    return words;
+}
+
+// Exclusive prefix of `count` over the tiles of one chain, in tile order, for
+// tile t of T.  `chain` points at the chain's status words.  Needs at least
+// kLevels waves in the block; lds holds one word per wave.  Every thread gets
+// the result.  Contains two block barriers.
+__device__ __forceinline__ uint32_t hier_prefix(uint64_t* chain, uint64_t* err, uint32_t t,
+                                                uint32_t T, uint32_t epoch, uint32_t count,
+                                                uint32_t* lds) {
     const int lane = threadIdx.x & 63;
-    if (tile == seg_first) {
-        if (lane == 0) st_agent(&status[tile], pack_status(epoch, kFlagPfx, aggregate));
-        return 0;
-    }
-    if (lane == 0) st_agent(&status[tile], pack_status(epoch, kFlagAgg, aggregate));
-    uint32_t exclusive = 0;
-    int64_t pos = static_cast<int64_t>(tile) - 1;
-    for (;;) {
-        const int64_t idx = pos - lane;
-        uint32_t flag = kFlagPfx, value = 0;
-        if (idx >= static_cast<int64_t>(seg_first)) {
-            const uint64_t w = poll_status(&status[idx], ld_agent(&status[idx]), epoch, err);
-            flag = static_cast<uint32_t>(w >> 32) & 3u;
-            value = static_cast<uint32_t>(w);
+    const int wave = threadIdx.x >> 6;
+    uint32_t part = 0;
+    if (wave < kLevels) {
+        // this level's word array and the tile's group index g at this level
+        uint64_t* level = chain;
+        uint32_t n = T;
+        for (int l = 0; l < wave; ++l) {
+            level += n;
+            n = (n + 63) >> 6;
         }
-        const uint64_t pfx = __ballot(flag == kFlagPfx);
-        // lanes up to and including the nearest prefix contribute
-        const int nearest = pfx ? (__ffsll(static_cast<unsigned long long>(pfx)) - 1) : 64;
-        exclusive += wave_sum(lane <= nearest ? value : 0u);
-        if (pfx) break;
-        pos -= 64;
+        const uint32_t g = t >> (6 * wave);
+        const uint32_t d = g & 63u;   // earlier siblings inside the parent group
+        // this tile closes its parent group at this level (it is the group's
+        // last tile, or the chain's last): it then publishes the group total
+        const uint32_t pspan = 1u << (6 * (wave + 1));
+        const bool publish = (((t & (pspan - 1)) == pspan - 1) || t == T - 1) && wave + 1 < kLevels;
+        if (wave == 0 && lane == 0) st_agent(&level[g], pack_status(epoch, kFlagAgg, count));
+        uint32_t v = 0;
+        // lanes [0, d) read the earlier siblings; above level 0, lane d reads
+        // the tile's own group word (published by the wave below) when the
+        // parent total is needed
+        if (lane < d || (lane == d && wave > 0 && publish)) {
+            const uint32_t idx = g - d + lane;
+            v = static_cast<uint32_t>(poll_status(&level[idx], ld_agent(&level[idx]), epoch, err));
+        }
+        const uint32_t own = (wave == 0) ? count : 0u;   // level 0: the tile's own count
+        part = wave_sum(lane < d ? v : 0u);
+        if (publish) {
+            const uint32_t incl = wave_sum(v) + own;     // siblings + own group word
+            if (lane == 0) st_agent(&(level + n)[g >> 6], pack_status(epoch, kFlagAgg, incl));
+        }
     }
-    if (lane == 0) st_agent(&status[tile], pack_status(epoch, kFlagPfx, exclusive + aggregate));
-    return exclusive;
+    __syncthreads();
+    if (lane == 0) lds[wave] = part;
+    __syncthreads();
+    uint32_t total = 0;
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) total += lds[l];
+    return total;
 }
 
 // Ranks the ITEMS flags of every lane of a WAVES-wave block over one tile.
@@ -138,8 +176,8 @@ __device__ __forceinline__ uint32_t lookback(uint64_t* status, uint64_t* err, ui
 // array is preceded by the workspace header; status[-1] holds the error word.
 template <int WAVES, int ITEMS>
 __device__ __forceinline__ uint32_t rank_tile(const bool (&f)[ITEMS], uint32_t (&rank)[ITEMS],
-                                              uint64_t* status, uint32_t tile, uint32_t seg_first,
-                                              uint32_t epoch, uint32_t* lds,
+                                              uint64_t* chain, uint64_t* err, uint32_t t,
+                                              uint32_t T, uint32_t epoch, uint32_t* lds,
                                               uint32_t* tile_total) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -159,35 +197,29 @@ __device__ __forceinline__ uint32_t rank_tile(const bool (&f)[ITEMS], uint32_t (
         wave_excl += (w < wave) ? v : 0u;
         total += v;
     }
-    if (wave == 0) {
-        const uint32_t ex = lookback(status, status - 1, tile, seg_first, epoch, total);
-        if (lane == 0) lds[WAVES] = ex;
-    }
-    __syncthreads();
-    const uint32_t tile_excl = lds[WAVES];
+    const uint32_t tile_excl = hier_prefix(chain, err, t, T, epoch, total, lds);
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) rank[i] += tile_excl + wave_excl;
     *tile_total = total;
     return tile_excl;
 }
 
-// Tile-wide exclusive prefix of one count per thread (0 <= c < 32), in thread
+// Tile-wide exclusive prefix of one count per thread (0 <= c < 64), in thread
 // order: the wave part is a sum of bit-plane ballots (lane rank among lanes
 // with bit b set, times 2^b), the block part an LDS scan of wave totals, the
-// tile part the decoupled look-back.  *thread_excl receives this thread's
+// tile part the hierarchical look-back.  *thread_excl receives this thread's
 // exclusive rank within the tile, *tile_total the tile's total; returns the
-// tile's exclusive prefix within its segment.  lds holds WAVES + 1 words.
-// Ends with a block barrier.
+// tile's exclusive prefix within its chain.  lds holds WAVES + 1 words.
 template <int WAVES>
 __device__ __forceinline__ uint32_t rank_counts(uint32_t c, uint32_t* thread_excl,
-                                                uint64_t* status, uint32_t tile,
-                                                uint32_t seg_first, uint32_t epoch, uint32_t* lds,
+                                                uint64_t* chain, uint64_t* err, uint32_t t,
+                                                uint32_t T, uint32_t epoch, uint32_t* lds,
                                                 uint32_t* tile_total) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     uint32_t excl = 0, wtot = 0;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < 6; ++b) {
         const uint64_t bal = __ballot((c >> b) & 1u);
         excl += lane_rank(bal) << b;
         wtot += static_cast<uint32_t>(__popcll(bal)) << b;
@@ -201,14 +233,10 @@ __device__ __forceinline__ uint32_t rank_counts(uint32_t c, uint32_t* thread_exc
         wave_excl += (w < wave) ? v : 0u;
         total += v;
     }
-    if (wave == 0) {
-        const uint32_t ex = lookback(status, status - 1, tile, seg_first, epoch, total);
-        if (lane == 0) lds[WAVES] = ex;
-    }
-    __syncthreads();
+    const uint32_t tile_excl = hier_prefix(chain, err, t, T, epoch, total, lds);
     *thread_excl = wave_excl + excl;
     *tile_total = total;
-    return lds[WAVES];
+    return tile_excl;
 }
 
 // Sum of the values published (with this epoch) by status[0 .. count), read

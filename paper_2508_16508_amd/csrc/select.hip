@@ -19,8 +19,8 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kBlock = kWaves * 64;
-constexpr int kSlotsPerLane = 16;
-constexpr int64_t kTile = int64_t(kBlock) * kSlotsPerLane;
+constexpr int kSlotsPerLane = 32;
+constexpr int64_t kTile = int64_t(kBlock) * kSlotsPerLane;   // 8192 slots
 
 enum SelMode : int { kSelDense = 0, kSelIndirect = 1, kAddDense = 2, kCompact = 3 };
 
@@ -43,25 +43,27 @@ struct SelArgs {
     int32_t vec_ok;           // mask / alive allow 16-byte loads
 };
 
-// Selection bits of the 16 consecutive slots [first, first + 16): bit k is
-// slot first + k.  One 16-byte load of the mask (or four of alive) per lane.
+// Selection bits of the 32 consecutive slots [first, first + 32): bit k is
+// slot first + k.  Two 16-byte loads of the mask (or eight of alive) per lane.
 template <int MODE>
 __device__ __forceinline__ uint32_t load_bits(const SelArgs& a, int64_t first) {
     uint32_t bits = 0;
     if (a.vec_ok && first + kSlotsPerLane <= a.n) {
         if (MODE == kAddDense) {
             const int4* p = reinterpret_cast<const int4*>(a.alive + first);
+            int4 v[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int4 v = p[q];
-                bits |= uint32_t(v.x == 0) << (4 * q) | uint32_t(v.y == 0) << (4 * q + 1) |
-                        uint32_t(v.z == 0) << (4 * q + 2) | uint32_t(v.w == 0) << (4 * q + 3);
-            }
+            for (int q = 0; q < 8; ++q) v[q] = p[q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                bits |= uint32_t(v[q].x == 0) << (4 * q) | uint32_t(v[q].y == 0) << (4 * q + 1) |
+                        uint32_t(v[q].z == 0) << (4 * q + 2) | uint32_t(v[q].w == 0) << (4 * q + 3);
         } else {
-            const uint4 m = *reinterpret_cast<const uint4*>(a.mask + first);
-            const uint32_t w[4] = {m.x, m.y, m.z, m.w};
+            const uint4* p = reinterpret_cast<const uint4*>(a.mask + first);
+            const uint4 m0 = p[0], m1 = p[1];
+            const uint32_t w[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 8; ++q)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     bits |= uint32_t(((w[q] >> (8 * b)) & 0xFFu) != 0u) << (4 * q + b);
@@ -77,11 +79,14 @@ __device__ __forceinline__ uint32_t load_bits(const SelArgs& a, int64_t first) {
     return bits;
 }
 
-// One tile of 4096 slots per block.  Phase 1 ranks the tile's selected slots
-// (lane-major: lane t owns slots [16 t, 16 t + 16) of the tile) and writes
-// their tile-local offsets, in rank order, into LDS.  Phase 2 walks those rank
-// positions with consecutive threads, so the reads of records j, j+1, ... are
-// contiguous and every load/store batch is branch-free.
+// One tile of 8192 slots per block (a 2^24-slot launch is one round of
+// resident blocks).  Phase 1 ranks the tile's selected slots (lane-major: lane
+// t owns slots [32 t, 32 t + 32) of the tile) and writes their tile-local
+// offsets, in rank order, into LDS.  Phase 2 walks those rank positions with
+// consecutive threads, so the reads of records j, j+1, ... are contiguous and
+// every load/store batch is branch-free.  (Rewriting whole destination lines
+// instead would not pay: a partial 4-byte write costs the memory a line read
+// and write, but so does reading the line to fill in the unselected slots.)
 //
 // NA is the attribute count rounded up to 1, 2, 4, 8 or 16; the host repeats
 // the last attribute's pointers in the padding entries (the repeated copy
@@ -94,25 +99,33 @@ __global__ __launch_bounds__(kBlock) void k_select(SelArgs a) {
     const uint32_t tile = blockIdx.x;
     const uint32_t epoch = read_epoch(a.epoch);
     const int64_t tbase = int64_t(tile) * kTile;
-    uint32_t bits = load_bits<MODE>(a, tbase + int64_t(threadIdx.x) * kSlotsPerLane);
+    const int64_t lbase = tbase + int64_t(threadIdx.x) * kSlotsPerLane;
+    const uint32_t bits0 = load_bits<MODE>(a, lbase);
 
-    uint32_t r, total;
-    const uint32_t tile_excl =
-        rank_counts<kWaves>(__popc(bits), &r, a.status, tile, 0u, epoch, lds, &total);
-    while (bits) {
-        const uint32_t k = __ffs(bits) - 1;
-        bits &= bits - 1;
-        pos[r++] = uint16_t(threadIdx.x * kSlotsPerLane + k);
-    }
-    __syncthreads();
+    uint32_t r0, total;
+    const uint32_t tile_excl = rank_counts<kWaves>(__popc(bits0), &r0, a.status, a.status - 1,
+                                                   tile, a.ntiles, epoch, lds, &total);
 
     if (MODE == kCompact) {
-        for (uint32_t p = threadIdx.x; p < total; p += kBlock)
-            a.out_idx[int64_t(tile_excl) + p] = int32_t(tbase + pos[p]);
+        uint32_t bits = bits0, r = r0;
+        while (bits) {
+            const uint32_t k = __ffs(bits) - 1;
+            bits &= bits - 1;
+            a.out_idx[int64_t(tile_excl) + r++] = int32_t(lbase + k);
+        }
         if (tile == a.ntiles - 1 && threadIdx.x == 0) *a.d_applied = int64_t(tile_excl) + total;
         return;
     }
 
+    {
+        uint32_t bits = bits0, r = r0;
+        while (bits) {
+            const uint32_t k = __ffs(bits) - 1;
+            bits &= bits - 1;
+            pos[r++] = uint16_t(threadIdx.x * kSlotsPerLane + k);
+        }
+    }
+    __syncthreads();
     const int64_t q = (MODE == kSelIndirect) ? *a.d_q : a.q;
     const int64_t room = q - int64_t(tile_excl);
     const uint32_t lim = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);

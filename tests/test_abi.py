@@ -115,3 +115,32 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         pkg.lib()
+
+
+def test_struct_layouts_match_header(abm, tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets
+    (compiled with the host C compiler against include/abm.h)."""
+    import ctypes as C
+    structs = {"abm_soa": abm.Soa, "abm_records": abm.Records,
+               "abm_predation_params": abm.PredationParams, "abm_species": abm.SpeciesPtrs,
+               "abm_predation_state": abm.PredationStatePtrs, "abm_model_desc": abm.ModelDesc,
+               "abm_batch": abm.Batch, "abm_tuning": abm.Tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "abm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        py = structs[cname]
+        if field == "size":
+            assert C.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, field).offset == int(val), (cname, field)

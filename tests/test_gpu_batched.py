@@ -1,0 +1,128 @@
+"""GPU parity of the batched predation form (many uneven models, one launch).
+
+Each model of a batch must be bit-identical to the same model run alone by the
+oracle: grass countdowns, every species array (stale fields included), the
+step counter, the live counts and the agent-update count (live agents at the
+start of each step, summed).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_16508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("x", "y", "e", "alive")
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+def _params(abm, orc, **kw):
+    return abm.predation_params(**kw), orc.pred_params(**kw)
+
+
+def _check_model(abm, orc, batch, m, kw, steps, countdown):
+    P = orc.pred_params(**kw)
+    S = orc.predation_init(P)
+    st = orc.predation_run(P, S, steps)
+    grass, sheep, wolves = batch.model_state(m, countdown)
+    assert np.array_equal(_host(grass), S.grass), (m, "grass")
+    for name, g, o in (("sheep", sheep, S.sheep), ("wolves", wolves, S.wolves)):
+        for f in FIELDS:
+            a, b = _host(g[f]), o[f]
+            if not np.array_equal(a, b):
+                bad = np.flatnonzero(a != b)
+                raise AssertionError(f"model {m} {name}.{f}: {bad.size} differ, first {bad[:5]} "
+                                     f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+    d = batch.descriptors()[m]
+    assert d.step == steps
+    assert d.updates == sum(s["live_s"] + s["live_w"] for s in st)
+    assert d.live_s == int(np.count_nonzero(S.sheep["alive"]))
+    assert d.live_w == int(np.count_nonzero(S.wolves["alive"]))
+
+
+def _mixed_models(seed, n):
+    g = np.random.default_rng(seed)
+    out = []
+    for m in range(n):
+        Wd = int(g.integers(1, 41))
+        Hd = int(g.integers(1, 41))
+        cells = Wd * Hd
+        cap_s = int(g.integers(1, max(2, cells // 2) + 1))
+        cap_w = int(g.integers(1, max(2, cells // 6) + 1))
+        kw = dict(W=Wd, H=Hd, R=int(g.integers(1, 12)), seed=int(g.integers(0, 2 ** 32)),
+                  cap_s=cap_s, cap_w=cap_w, n_s0=int(g.integers(0, cap_s + 1)),
+                  n_w0=int(g.integers(0, cap_w + 1)), T_s=int(g.integers(0, 2 ** 31)),
+                  T_w=int(g.integers(0, 2 ** 31)))
+        out.append(kw)
+    return out
+
+
+@pytest.mark.parametrize("block,items", [(256, 1), (512, 2), (512, 4), (1024, 8)])
+def test_mixed_batch_matches_models_alone(abm, orc, block, items):
+    """40 models of random shapes (1x1 up to 40x40, tiny and overflowing
+    capacities, different regrowth delays, seeds and reproduction rates),
+    different step targets, advanced in three launches of at most 12 steps."""
+    kws = _mixed_models(block + items, 40)
+    targets = [int(t) for t in np.random.default_rng(7).integers(0, 31, size=len(kws))]
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], targets,
+                                 block_threads=block, items=items)
+    batch.init()
+    for _ in range(3):
+        batch.run(12)
+    torch.cuda.synchronize()
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, min(targets[m], 36), cd)
+
+
+def test_small_workload_in_a_batch(abm, orc):
+    """The 64x64 model (seeds 0-7) inside a batch for all 200 steps."""
+    kws = [dict(seed=s) for s in range(8)]
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 200)
+    batch.init()
+    batch.run(200)
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, 200, cd)
+
+
+def test_uneven_workload_sample(abm, orc):
+    """Models of the 4096-model workload recipe (side 32-256, sheep = cells/10,
+    wolves = cells/40, capacities 4x): the smallest, the largest and a spread
+    between, 60 steps."""
+    specs = W.batched_models(0, 4096)
+    by_side = sorted(range(len(specs)), key=lambda m: specs[m].side)
+    pick = [by_side[i] for i in (0, 1, 500, 1500, 2500, 3500, 4094, 4095)]
+    kws = []
+    for m in pick:
+        sp = specs[m]
+        kws.append(dict(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s, cap_w=sp.cap_w,
+                        n_s0=sp.n_s0, n_w0=sp.n_w0))
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 60)
+    batch.init()
+    batch.run(25)
+    batch.run(35)
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, 60, cd)
+
+
+def test_batched_equals_one_model_path(abm):
+    """The same model advanced by the batched launch and by the one-model
+    multi-launch path ends in identical bytes."""
+    kw = dict(W=96, H=80, seed=33, cap_s=3000, cap_w=800, n_s0=700, n_w0=200)
+    batch = abm.BatchedPredation([abm.predation_params(**kw)] * 3, [50, 50, 20])
+    batch.init()
+    batch.run(50)
+    plain = abm.predation_init(abm.predation_params(**kw))
+    plain.run(50)
+    grass, sheep, wolves = batch.model_state(1)
+    assert torch.equal(grass, plain.grass)
+    for f in FIELDS:
+        assert torch.equal(sheep[f], plain.sheep[f]) and torch.equal(wolves[f], plain.wolves[f])
+    d = batch.descriptors()
+    assert (d[0].step, d[1].step, d[2].step) == (50, 50, 20)

@@ -14,7 +14,7 @@ from paper_2508_16508_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [0, 1, 63, 64, 65, 1000, 4095, 4096, 4097, 3 * 4096 + 77, 100_003]
+SIZES = [0, 1, 63, 64, 65, 1000, 4095, 4096, 4097, 4096 + 3000, 3 * 4096 + 77, 100_003]
 
 
 def dev(a):
