@@ -159,6 +159,28 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
             "batched_over_plain": rate_b / rate_p}
 
 
+def served_leg(seconds, rate=200.0):
+    """Served form: Poisson arrivals (rate/s for `seconds`), grid side log-uniform
+    in [32, 1024], steps log-uniform in [100, 5000], admitted by HBM footprint
+    into the running batched launch; open-loop latency from scheduled arrival."""
+    from paper_2508_16508_amd import serve as S
+    from paper_2508_16508_amd import workloads as W
+    trace = W.served_trace(0, rate=rate, duration_s=seconds)
+    reqs = S.requests_from_trace(trace)
+    cells, sheep, wolves = 400_000_000, 160_000_000, 40_000_000
+    runner = S.GpuRunner(cells, sheep, wolves,
+                         max_model_cap=max(max(q.cap_s, q.cap_w) for q in reqs))
+    sch = S.Scheduler(runner, cells, sheep, wolves,
+                      log=lambda m: print("served:", m, file=sys.stderr, flush=True))
+    rep = sch.serve(reqs)
+    out = rep.summary()
+    out["workload"] = (f"Poisson arrivals at {rate:g}/s for {seconds:g} s ({len(reqs)} requests), "
+                       "side log-uniform [32, 1024], steps log-uniform [100, 5000], "
+                       "sheep = cells/10, wolves = cells/40, capacities 4x")
+    out["pools"] = {"cells": cells, "sheep_slots": sheep, "wolf_slots": wolves}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +190,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=60.0,
+                    help="length of the served request trace (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -286,6 +310,10 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg(abm, W, torch)
+        torch.cuda.empty_cache()
+    if args.served_seconds > 0:
+        out["served"] = served_leg(args.served_seconds)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
