@@ -46,15 +46,15 @@ def algorithmic_bytes(op, n, k):
     raise ValueError(op)
 
 
-def _profile_traffic(kernel_sources_hash):
-    """HBM traffic per launch of the dominant kernel from the committed PMC
-    summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "select_update_microbench_pmc.txt")
+def _profile_traffic(kernel_sources_hash, op):
+    """HBM traffic per launch of `op` (mean over the densities) from the
+    committed PMC summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "select_update_microbench_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    t = re.search(r"traffic_bytes_per_launch\[" + op + r"\]:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_sources_hash:
         return None
     return float(t.group(1))
@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device 3 times (a transfer of known size "
+                         "for scaling hardware byte counters)")
     ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served request trace (0 = skip)")
     args = ap.parse_args()
@@ -205,6 +208,13 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # ---- resident inputs: per seed and density, mask + records + alive
     sets = []
@@ -286,7 +296,7 @@ def main():
     dom = max(ops, key=lambda o: kernels[o]["total_ms"])
     kd = kernels[dom]
     src_hash = kernel_sources_hash()
-    traffic = _profile_traffic(src_hash) if dom == "select_update" else None
+    traffic = _profile_traffic(src_hash, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
