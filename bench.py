@@ -98,10 +98,20 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     launches of `chunk` steps each, against the one-model multi-launch path
     timed on a stratified subset of the same models (rates in agent updates/s;
     both paths compute bit-identical states)."""
+    from paper_2508_16508_amd.tune import autotune_batched
     specs = W.batched_models(0, 4096)
     params = [abm.predation_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s,
                                    cap_w=sp.cap_w, n_s0=sp.n_s0, n_w0=sp.n_w0) for sp in specs]
-    batch = abm.BatchedPredation(params, steps)
+    def make(block, items):
+        b = abm.BatchedPredation(params, 1000, block_threads=block, items=items)
+        b.init()
+        return b
+
+    # tuned on the batch itself (occupancy depends on how many models compete)
+    tuning = autotune_batched(make, "batched:4096 models side 32-256", steps=4, use_cache=False)
+    torch.cuda.empty_cache()
+    batch = abm.BatchedPredation(params, steps, block_threads=tuning["block_threads"],
+                                 items=tuning["items"])
     batch.init()
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
@@ -156,7 +166,9 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
             "plain_agent_updates_per_s": rate_p,
             "plain_sample": f"{len(pick)} models (every {len(specs) // plain_models}th by size), "
                             f"{plain_steps} steps each, one-model multi-launch path",
-            "batched_over_plain": rate_b / rate_p}
+            "batched_over_plain": rate_b / rate_p,
+            "tuning": {"block_threads": tuning["block_threads"], "items": tuning["items"],
+                       "candidates_ms_per_4_steps": tuning["timings_ms"]}}
 
 
 def served_leg(seconds, rate=200.0):

@@ -218,6 +218,45 @@ ABM_API int abm_predation_step(const abm_predation_params* p, abm_predation_stat
                        void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched primitives: many independent collections of uneven sizes, packed
+ * back to back, each processed exactly as the single-collection call above
+ * would process it alone (the paper vectorises its manipulation functions
+ * over Sets, Sec. 2).  Segment m owns slots [slot_off[m], slot_off[m+1]) of
+ * the packed collection and records [rec_off[m], rec_off[m+1]) of the packed
+ * records.  Offsets are DEVICE int64 arrays of n_segments + 1 entries,
+ * non-decreasing, with slot_off[0] = 0, slot_off[n_segments] = capacity and
+ * rec_off[n_segments] <= record count (results are undefined otherwise).
+ * Counts are device int64 arrays of n_segments entries.  Workspace: as for
+ * the single call with capacity = the packed slot count.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_select_update_batched(int32_t n_segments, const abm_soa* dst,
+                                      const int64_t* slot_off, const uint8_t* sel_mask,
+                                      const abm_records* upd, const int64_t* rec_off,
+                                      int64_t* d_applied, int64_t* d_dropped, void* ws,
+                                      size_t ws_bytes, void* stream);
+
+ABM_API int abm_add_agents_batched(int32_t n_segments, const abm_soa* dst, const int64_t* slot_off,
+                                   const abm_records* newborn, const int64_t* rec_off,
+                                   int64_t* d_added, int64_t* d_dropped, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+ABM_API int abm_remove_agents_batched(int32_t n_segments, const abm_soa* dst,
+                                      const int64_t* slot_off, const uint8_t* kill_mask,
+                                      int64_t* d_removed, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* Claims [claim_off[m], claim_off[m+1]) compete for targets
+ * [target_off[m], target_off[m+1]) of the packed best/winner arrays; target[c]
+ * is segment-local, the key uses the segment-local claim index, and winner[t]
+ * holds that local index (or -1). */
+ABM_API int abm_resolve_conflicts_batched(int32_t n_segments, const int64_t* claim_off,
+                                          int64_t n_claims, const int32_t* target,
+                                          const uint32_t* prio, const uint8_t* active,
+                                          const int64_t* target_off, int64_t n_targets,
+                                          uint64_t* best, int32_t* winner, uint8_t* won,
+                                          void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched predation: many independent models of uneven sizes advanced by one
  * persistent launch (the paper vectorises identical models, Sec. 2 and
  * Table 2; here shapes may differ).  Every model follows exactly the one-model

@@ -28,6 +28,8 @@ EXPORTED = (
     "abm_add_agents", "abm_remove_agents", "abm_resolve_conflicts", "abm_predation_init",
     "abm_predation_step", "abm_last_error", "abm_version", "abm_batched_workspace_bytes",
     "abm_predation_batched_init", "abm_predation_run_batched", "abm_predation_batched_grass",
+    "abm_select_update_batched", "abm_add_agents_batched", "abm_remove_agents_batched",
+    "abm_resolve_conflicts_batched",
 )
 
 
@@ -105,6 +107,13 @@ def lib():
         L.abm_predation_run_batched.argtypes = [C.POINTER(Batch), vp, i32, C.POINTER(Tuning), vp,
                                                 sz, vp]
         L.abm_predation_batched_grass.argtypes = [C.POINTER(Batch), vp, vp]
+        L.abm_select_update_batched.argtypes = [i32, C.POINTER(Soa), vp, vp, C.POINTER(Records), vp,
+                                                vp, vp, vp, sz, vp]
+        L.abm_add_agents_batched.argtypes = [i32, C.POINTER(Soa), vp, C.POINTER(Records), vp, vp,
+                                             vp, vp, sz, vp]
+        L.abm_remove_agents_batched.argtypes = [i32, C.POINTER(Soa), vp, vp, vp, vp, sz, vp]
+        L.abm_resolve_conflicts_batched.argtypes = [i32, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp,
+                                                    vp]
         L.abm_last_error.restype = C.c_char_p
         L.abm_version.restype = C.c_char_p
         for name in EXPORTED:
@@ -277,6 +286,82 @@ def resolve_conflicts(target, prio, n_targets, active=None, best=None, winner=No
         won = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
     _check(lib().abm_resolve_conflicts(n, _p(target), _p(prio), _p(active), n_targets, _p(best),
                                        _p(winner), _p(won), _stream(stream)))
+    return best, winner, won
+
+
+# ---------------------------------------------------------------- batched primitives
+
+def _offsets(off, name):
+    _require(off, torch.int64, name)
+    return off.numel() - 1
+
+
+def select_update_batched(attrs, slot_off, sel_mask, recs, rec_off, ws=None, applied=None,
+                          dropped=None, stream=None):
+    """select_update on every segment of packed collections (device offsets).
+    Returns per-segment (applied, dropped) int64 device tensors."""
+    n_seg = _offsets(slot_off, "slot_off")
+    _offsets(rec_off, "rec_off")
+    dst, upd = make_soa(attrs), make_records(recs)
+    _require(sel_mask, torch.uint8, "sel_mask")
+    dev = slot_off.device
+    if ws is None:
+        ws = workspace(dst.capacity, ABM_OP_SELECT_UPDATE, dev, stream)
+    applied = applied if applied is not None else torch.zeros(max(1, n_seg), dtype=torch.int64,
+                                                               device=dev)
+    dropped = dropped if dropped is not None else torch.zeros(max(1, n_seg), dtype=torch.int64,
+                                                               device=dev)
+    _check(lib().abm_select_update_batched(n_seg, C.byref(dst), _p(slot_off), _p(sel_mask),
+                                           C.byref(upd), _p(rec_off), _p(applied), _p(dropped),
+                                           _p(ws), ws.numel(), _stream(stream)))
+    return applied, dropped
+
+
+def add_agents_batched(attrs, alive, slot_off, recs, rec_off, ws=None, stream=None):
+    n_seg = _offsets(slot_off, "slot_off")
+    _offsets(rec_off, "rec_off")
+    dst, nb = make_soa(attrs, alive), make_records(recs)
+    dev = slot_off.device
+    if ws is None:
+        ws = workspace(dst.capacity, ABM_OP_ADD_AGENTS, dev, stream)
+    added = torch.zeros(max(1, n_seg), dtype=torch.int64, device=dev)
+    dropped = torch.zeros(max(1, n_seg), dtype=torch.int64, device=dev)
+    _check(lib().abm_add_agents_batched(n_seg, C.byref(dst), _p(slot_off), C.byref(nb),
+                                        _p(rec_off), _p(added), _p(dropped), _p(ws), ws.numel(),
+                                        _stream(stream)))
+    return added, dropped
+
+
+def remove_agents_batched(alive, slot_off, kill_mask, ws=None, stream=None):
+    n_seg = _offsets(slot_off, "slot_off")
+    _require(alive, torch.int32, "alive")
+    _require(kill_mask, torch.uint8, "kill_mask")
+    s = Soa()
+    s.n_attrs = 0
+    s.capacity = alive.numel()
+    s.alive = alive.data_ptr()
+    dev = slot_off.device
+    if ws is None:
+        ws = workspace(alive.numel(), ABM_OP_REMOVE_AGENTS, dev, stream)
+    removed = torch.zeros(max(1, n_seg), dtype=torch.int64, device=dev)
+    _check(lib().abm_remove_agents_batched(n_seg, C.byref(s), _p(slot_off), _p(kill_mask),
+                                           _p(removed), _p(ws), ws.numel(), _stream(stream)))
+    return removed
+
+
+def resolve_conflicts_batched(claim_off, target, prio, target_off, active=None, stream=None):
+    """Returns packed (best, winner, won); winner holds segment-local claim indices."""
+    n_seg = _offsets(claim_off, "claim_off")
+    _offsets(target_off, "target_off")
+    n = target.numel()
+    nt = int(target_off[-1].item())
+    dev = target.device
+    best = torch.empty(max(1, nt), dtype=torch.uint64, device=dev)
+    winner = torch.empty(max(1, nt), dtype=torch.int32, device=dev)
+    won = torch.empty(max(1, n), dtype=torch.uint8, device=dev)
+    _check(lib().abm_resolve_conflicts_batched(n_seg, _p(claim_off), n, _p(target), _p(prio),
+                                               _p(active), _p(target_off), nt, _p(best),
+                                               _p(winner), _p(won), _stream(stream)))
     return best, winner, won
 
 

@@ -126,3 +126,23 @@ def test_batched_equals_one_model_path(abm):
         assert torch.equal(sheep[f], plain.sheep[f]) and torch.equal(wolves[f], plain.wolves[f])
     d = batch.descriptors()
     assert (d[0].step, d[1].step, d[2].step) == (50, 50, 20)
+
+
+def test_autotuner_picks_a_candidate_and_caches_it(abm, tmp_path):
+    from paper_2508_16508_amd.tune import autotune_batched
+    kws = [dict(W=40 + m, H=30, seed=m, cap_s=900, cap_w=200, n_s0=120, n_w0=30)
+           for m in range(16)]
+
+    def make(block, items):
+        b = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 100,
+                                 block_threads=block, items=items)
+        b.init()
+        return b
+
+    path = str(tmp_path / "tune.json")
+    cands = ((256, 2), (512, 4))
+    first = autotune_batched(make, "test", steps=3, candidates=cands, cache_path=path)
+    assert not first["cached"] and (first["block_threads"], first["items"]) in cands
+    assert set(first["timings_ms"]) == {"256x2", "512x4"}
+    again = autotune_batched(make, "test", steps=3, candidates=cands, cache_path=path)
+    assert again["cached"] and again["block_threads"] == first["block_threads"]
