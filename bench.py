@@ -171,6 +171,29 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
                        "candidates_ms_per_4_steps": tuning["timings_ms"]}}
 
 
+def predation_leg(abm, torch, kw, steps, label):
+    """One model on the one-model path (four launches per step): agent updates
+    per second over `steps` steps (live agents at the start of each step)."""
+    model = abm.predation_init(abm.predation_params(**kw))
+    stats = torch.zeros((steps, 8), dtype=torch.int64, device="cuda")
+    model.run(1)                                   # warm-up step
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    model.run(steps, stats)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = int(stats[:, 0].sum().item() + stats[:, 1].sum().item())
+    err = abm.workspace_error(model.ws)
+    del model, stats
+    torch.cuda.empty_cache()
+    return {"workload": label, "steps": steps, "ms": ms, "us_per_step": 1e3 * ms / steps,
+            "agent_updates": upd, "agent_updates_per_s": upd / (ms / 1e3),
+            "workspace_error": err}
+
+
 def served_leg(seconds, rate=200.0):
     """Served form: Poisson arrivals (rate/s for `seconds`), grid side log-uniform
     in [32, 1024], steps log-uniform in [100, 5000], admitted by HBM footprint
@@ -331,6 +354,15 @@ def main():
     del sets, dst
     torch.cuda.empty_cache()
     if not args.no_batched:
+        out["predation_small"] = predation_leg(
+            abm, torch, dict(seed=0), 199,
+            "64x64 torus, 400 sheep / 100 wolves in 4096 / 1024 slots, steps 1-199 after a "
+            "warm-up step")
+        out["predation_large"] = predation_leg(
+            abm, torch, dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
+                             n_w0=400_000, seed=0), 999,
+            "2048x2048 torus, 1.6M sheep / 0.4M wolves in 2^24 / 2^22 slots, steps 1-999 "
+            "after a warm-up step")
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()
     if args.served_seconds > 0:
