@@ -60,11 +60,19 @@ def _profile_traffic(kernel_sources_hash, op):
     return float(t.group(1))
 
 
+# The files the microbenchmark's kernels (select, add, remove) are built from.
+MICROBENCH_SOURCES = ("include/abm.h", "paper_2508_16508_amd/csrc/api.hip",
+                      "paper_2508_16508_amd/csrc/common.hpp", "paper_2508_16508_amd/csrc/scan.hpp",
+                      "paper_2508_16508_amd/csrc/select.hip", "paper_2508_16508_amd/csrc/remove.hip",
+                      "paper_2508_16508_amd/_build.py")
+
+
 def kernel_sources_hash():
+    """Hash of the microbenchmark kernels' sources and build flags: a counter
+    summary taken on other sources no longer describes these kernels."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2508_16508_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+    for name in MICROBENCH_SOURCES:
+        with open(os.path.join(ROOT, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
@@ -194,17 +202,22 @@ def predation_leg(abm, torch, kw, steps, label):
             "workspace_error": err}
 
 
-def served_leg(seconds, rate=200.0):
+def served_leg(seconds, rate=200.0, team_size=1, team_min_size=1 << 18):
     """Served form: Poisson arrivals (rate/s for `seconds`), grid side log-uniform
     in [32, 1024], steps log-uniform in [100, 5000], admitted by HBM footprint
-    into the running batched launch; open-loop latency from scheduled arrival."""
+    into the running batched launch; open-loop latency from scheduled arrival.
+    With team_size > 1, models of at least team_min_size cells plus slots
+    (side >= ~400) are each advanced by a team of team_size workgroups; under
+    this load that lowers throughput more than it shortens the long models, so
+    the default is one workgroup per model."""
     from paper_2508_16508_amd import serve as S
     from paper_2508_16508_amd import workloads as W
     trace = W.served_trace(0, rate=rate, duration_s=seconds)
     reqs = S.requests_from_trace(trace)
     cells, sheep, wolves = 400_000_000, 160_000_000, 40_000_000
     runner = S.GpuRunner(cells, sheep, wolves,
-                         max_model_cap=max(max(q.cap_s, q.cap_w) for q in reqs))
+                         max_model_cap=max(max(q.cap_s, q.cap_w) for q in reqs),
+                         team_size=team_size, team_min_size=team_min_size)
     sch = S.Scheduler(runner, cells, sheep, wolves,
                       log=lambda m: print("served:", m, file=sys.stderr, flush=True))
     rep = sch.serve(reqs)
@@ -213,6 +226,7 @@ def served_leg(seconds, rate=200.0):
                        "side log-uniform [32, 1024], steps log-uniform [100, 5000], "
                        "sheep = cells/10, wolves = cells/40, capacities 4x")
     out["pools"] = {"cells": cells, "sheep_slots": sheep, "wolf_slots": wolves}
+    out["teams"] = {"team_size": team_size, "team_min_size": team_min_size}
     return out
 
 
@@ -230,6 +244,8 @@ def main():
                          "for scaling hardware byte counters)")
     ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served request trace (0 = skip)")
+    ap.add_argument("--served-team-size", type=int, default=1,
+                    help="workgroups per team for the large models of the served leg (1 = none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -366,7 +382,7 @@ def main():
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()
     if args.served_seconds > 0:
-        out["served"] = served_leg(args.served_seconds)
+        out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

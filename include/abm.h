@@ -295,12 +295,19 @@ typedef struct abm_tuning {
     int32_t block_threads;         /* threads per model workgroup (multiple of 64 in [256, 1024]); 0 = 512 */
     int32_t workgroups;            /* persistent workgroups; 0 = as many as are resident at once */
     int32_t items;                 /* slots per thread per chunk: 1, 2, 4 or 8; 0 = 4 */
+    int32_t team_size;             /* workgroups per team (1..16); 0 or 1 = no teams */
+    int32_t team_models;           /* the first team_models entries of order run in teams */
+    int32_t team_workgroups;       /* workgroups formed into teams, a multiple of 8 * team_size;
+                                      0 = enough for team_models teams (capped by residency) */
 } abm_tuning;
 
-/* Workspace for abm_predation_run_batched: a breeder list per workgroup.  Its
- * 256-byte header ends with an error word (offset 248) that a run sets to 1
- * if some descriptor's cap_s + cap_w exceeds 2 * max_cap (that model is then
- * left untouched). */
+/* Workspace for abm_predation_run_batched with at most n_workgroups
+ * workgroups: a 256-byte header, a fixed team area and a breeder list per
+ * workgroup.  The header ends with an error word (offset 248) that a run sets
+ * to 1 if some descriptor's cap_s + cap_w exceeds 2 * max_cap (that model is
+ * then left untouched) or if a team barrier times out (a member never ran;
+ * the state of that team's model is then undefined).  Returns 0 for
+ * max_cap outside [1, 2^30] or n_workgroups outside [1, 8192]. */
 ABM_API size_t abm_batched_workspace_bytes(int64_t max_cap, int32_t n_workgroups);
 
 /* Initial state of every model (the one-model definition per model, with the
@@ -309,8 +316,15 @@ ABM_API int abm_predation_batched_init(const abm_batch* b, void* stream);
 
 /* Advance every model by min(max_steps, steps_target - step) steps.  order is
  * a device int32 permutation of [0, n_models): workgroups take models in that
- * order (largest first balances the load).  Afterwards each descriptor's
- * step, updates, live_s and live_w are current. */
+ * order (largest first balances the load).  With tune->team_size K > 1 the
+ * first tune->team_models entries of order are each advanced by a team of K
+ * workgroups that split the model's slots into K contiguous ranges and meet
+ * at three device-wide team barriers per step; the results are the same as
+ * with one workgroup per model.  Teams need 8 K resident workgroups (else
+ * ABM_E_INVALID).  The workspace must hold abm_batched_workspace_bytes(max_cap,
+ * n) bytes, n being the number of workgroups launched: at most the resident
+ * count (or tune->workgroups), which the caller can use as the bound.
+ * Afterwards each descriptor's step, updates, live_s and live_w are current. */
 ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, int32_t max_steps,
                                       const abm_tuning* tune, void* ws, size_t ws_bytes,
                                       void* stream);

@@ -73,7 +73,9 @@ class Batch(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("block_threads", C.c_int32), ("workgroups", C.c_int32), ("items", C.c_int32)]
+    _fields_ = [("block_threads", C.c_int32), ("workgroups", C.c_int32), ("items", C.c_int32),
+                ("team_size", C.c_int32), ("team_models", C.c_int32),
+                ("team_workgroups", C.c_int32)]
 
 
 _lib = None
@@ -452,9 +454,12 @@ class BatchedPredation:
 
     models: list of PredationParams (one per model); steps_target: per model
     (int or list).  Slot and cell ranges are packed in model order; the launch
-    order is largest model first."""
+    order is largest model first.  Models of at least team_min_size cells plus
+    slots are each advanced by a team of team_size workgroups (team_size 1: no
+    teams)."""
 
-    def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4):
+    def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4,
+                 team_size=1, team_min_size=1 << 18):
         self.params = list(models)
         n = len(self.params)
         tgt = [steps_target] * n if isinstance(steps_target, int) else list(steps_target)
@@ -483,8 +488,12 @@ class BatchedPredation:
         size = [p.W * p.H + p.cap_s + p.cap_w for p in self.params]
         order = sorted(range(n), key=lambda m: -size[m])
         self.order = torch.tensor(order or [0], dtype=torch.int32, device=device)
+        self.size = size
+        self.sorted_size = [size[m] for m in order]
         self.block_threads = block_threads
         self.items = items
+        self.team_size = team_size
+        self.team_min_size = team_min_size
         props = torch.cuda.get_device_properties(self.ready.device)
         self.workgroups = props.multi_processor_count * max(1, 2048 // block_threads)
         nbytes = int(lib().abm_batched_workspace_bytes(self.max_cap, self.workgroups))
@@ -501,10 +510,18 @@ class BatchedPredation:
         b = self._batch()
         _check(lib().abm_predation_batched_init(C.byref(b), _stream(stream)))
 
-    def run(self, max_steps: int, stream=None, block_threads=None, workgroups=None, items=None):
+    def team_models(self, team_min_size=None) -> int:
+        """Number of leading models of the launch order big enough for a team."""
+        lim = self.team_min_size if team_min_size is None else team_min_size
+        return sum(1 for v in self.sorted_size if v >= lim)
+
+    def run(self, max_steps: int, stream=None, block_threads=None, workgroups=None, items=None,
+            team_size=None, team_min_size=None, team_workgroups=0):
         b = self._batch()
+        k = self.team_size if team_size is None else team_size
+        nt = self.team_models(team_min_size) if k > 1 else 0
         t = Tuning(block_threads or self.block_threads, workgroups or self.workgroups,
-                   items or self.items)
+                   items or self.items, k, nt, team_workgroups)
         _check(lib().abm_predation_run_batched(C.byref(b), _p(self.order), max_steps, C.byref(t),
                                                _p(self.ws), self.ws.numel(), _stream(stream)))
 

@@ -48,9 +48,16 @@ struct BatchArgs {
     uint64_t* claims;          // packed, 3 words per cell
     int32_t *sx, *sy, *se, *sa;
     int32_t *wx, *wy, *we, *wa;
-    uint32_t* queue;           // model queue counter (reset before the launch)
+    uint32_t* queue;           // two model queue counters (reset before the launch)
     int32_t* scratch;          // per-workgroup breeder list
     int64_t scratch_stride;    // ints per workgroup
+    uint64_t* err;             // workspace error word
+    int32_t n_team;            // order[0, n_team) run in teams
+    uint32_t team_k;           // members per team
+    uint32_t team_wgs;         // workgroups in teams (multiple of 8 * team_k)
+    uint32_t* team_ctr;        // barrier counter per team
+    int32_t* team_mail;        // model mailbox per team
+    int32_t* team_counts;      // [workgroup][5] member counts
 };
 
 __device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t n) {
@@ -127,12 +134,77 @@ __device__ __forceinline__ bool on_grid(const ModelView& v, int32_t x, int32_t y
     return x >= 0 && x < v.W && y >= 0 && y < v.H;
 }
 
-// One step t of model v.  A chunk is blockDim * ITEMS slots; item k of lane l
-// of wave w is slot c0 + (w * ITEMS + k) * 64 + l, so each load instruction of
-// a wave covers 64 consecutive slots and the ITEMS loads of a lane are issued
-// together.  breeders: this workgroup's scratch list.
+// A team of K workgroups advancing one model together (K = 1: one workgroup
+// alone).  Member r owns the r-th contiguous K-th of each species' slots and
+// keeps its own breeder list; members exchange per-range counts.  Members of a
+// team are the workgroups base, base + 8, ..., base + 8 (K - 1): workgroups are
+// dispatched to the eight XCDs in turn, so the members normally share one L2.
+// Correctness does not rest on that: the team barrier uses agent-scope fences.
+constexpr int kMaxTeam = 16;
+constexpr int kCountWords = 5;   // breeders of both species, free slots of both, live
+constexpr int kMaxWorkgroups = 8 * 1024;
+
+struct Team {
+    int K, r;
+    uint32_t gen;               // team barriers passed
+    uint32_t* ctr;              // barrier counter (K > 1)
+    int32_t* scratch;           // lists of all workgroups
+    int64_t stride;             // ints per list
+    int32_t* counts;            // [workgroup][kCountWords]
+    uint32_t base;              // workgroup index of member 0
+    uint64_t* err;
+    int32_t* s_pre;             // LDS: breeder prefixes [2][kMaxTeam + 1], free prefix [2], live
+    int32_t* s_ok;              // LDS: barrier outcome
+};
+
+__device__ __forceinline__ int32_t* member_list(const Team& tm, int j) {
+    return tm.scratch + int64_t(tm.base + 8u * uint32_t(j)) * tm.stride;
+}
+
+// Team-wide barrier; false if a member never arrived (the error word is set).
+// Every wave waits until its own stores are performed at the L2, then the
+// workgroup barrier; thread 0 alone makes the L2 contents visible device-wide
+// (agent-scope release), counts the member in, waits for the others and
+// acquires (agent scope, which also drops the CU's stale L1 lines) before the
+// second workgroup barrier releases the other waves.  One release per member
+// instead of one per wave: every wave writing back the L2 costs ~10x more
+// when hundreds of workgroups are resident.
+__device__ __forceinline__ bool team_sync(Team& tm) {
+    if (tm.K == 1) {
+        __syncthreads();
+        return true;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(tm.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (tm.gen + 1) * uint32_t(tm.K);
+        int32_t ok = 1;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(tm.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kSpinLimit) {
+                st_agent(tm.err, 1ull);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *tm.s_ok = ok;
+    }
+    __syncthreads();
+    ++tm.gen;
+    return *tm.s_ok != 0;
+}
+
+// One step t of model v by team tm; false if the team barrier failed.  A chunk
+// is blockDim * ITEMS slots; item k of lane l of wave w is slot
+// c0 + (w * ITEMS + k) * 64 + l, so each load instruction of a wave covers 64
+// consecutive slots and the ITEMS loads of a lane are issued together.
 template <int ITEMS>
-__device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, uint32_t* lds,
+__device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* lds,
                            uint32_t* live_out) {
     const uint64_t skey = stream_key(v.seed, t);
     const uint32_t move_p[2] = {kSheepMove, kWolfMove};
@@ -140,16 +212,26 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t chunk = int32_t(blockDim.x) * ITEMS;
     const int32_t lbase = wave * ITEMS * 64 + lane;
+    // this member's slot range of each species; species 1's list follows species 0's
+    int32_t lo[2], hi[2];
+    const int32_t per0 = (v.cap[0] + tm.K - 1) / tm.K;
+    const int32_t per1 = (v.cap[1] + tm.K - 1) / tm.K;
+    lo[0] = min(v.cap[0], tm.r * per0);
+    hi[0] = min(v.cap[0], lo[0] + per0);
+    lo[1] = min(v.cap[1], tm.r * per1);
+    hi[1] = min(v.cap[1], lo[1] + per1);
+    int32_t* my_list = member_list(tm, tm.r);
 
     // ---- A: move + claims
     uint32_t live = 0;
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
-        for (int32_t c0 = 0; c0 < v.cap[s]; c0 += chunk) {
+        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < v.cap[s] ? v.al[s][i] : 0;
+                al[k] = i < hi[s] ? v.al[s][i] : 0;
             }
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
@@ -176,24 +258,28 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
             }
         }
     }
-    *live_out = block_sum32(live, lds);   // (barrier: claims complete)
+    live = block_sum32(live, lds);
+    if (!team_sync(tm)) return false;    // every claim of the step is posted
 
-    // ---- B: eat + breeder compaction (per species, ascending slots)
-    uint32_t nb[2];
+    // ---- B: eat, member-local breeder lists (ascending), free-slot counts
+    uint32_t nb_local[2], nf_local[2];
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
-        uint32_t base_rank = 0;
-        for (int32_t c0 = 0; c0 < v.cap[s]; c0 += chunk) {
+        uint32_t base_rank = 0, nfree = 0;
+        int32_t* list = my_list + (s ? per0 : 0);
+        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < v.cap[s] ? v.al[s][i] : 0;
+                al[k] = i < hi[s] ? v.al[s][i] : -1;
             }
             bool br[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 br[k] = false;
-                if (al[k] == 0) continue;
+                if (al[k] == 0) ++nfree;
+                if (al[k] <= 0) continue;
                 const int32_t i = c0 + lbase + k * 64;
                 const int32_t x = v.x[s][i], y = v.y[s][i];
                 int32_t e = v.e[s][i];
@@ -211,6 +297,7 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
                             ld_claim(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
                             v.al[0][i] = 2;   // eaten: dead, its claims still to be reset
                             eaten = true;
+                            ++nfree;
                         }
                     } else if (ld_claim(cw + 1) != kNoClaim &&
                                ld_claim(cw + 2) == key_of(skey, i, kWolfEatKey)) {
@@ -224,29 +311,82 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
             const uint32_t tot = chunk_rank<ITEMS>(br, rank, lds);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k)
-                if (br[k]) breeders[(s ? v.cap[0] : 0) + base_rank + rank[k]] = c0 + lbase + k * 64;
+                if (br[k]) list[base_rank + rank[k]] = c0 + lbase + k * 64;
             base_rank += tot;
         }
-        nb[s] = base_rank;
+        nb_local[s] = base_rank;
+        nf_local[s] = block_sum32(nfree, lds);
     }
-    __syncthreads();
+    // s_pre: [0, K] breeder prefix of species 0, [K+1, 2K+1] of species 1,
+    // then the free-slot prefix of this member for both species and the live total
+    int32_t* bpre0 = tm.s_pre;
+    int32_t* bpre1 = tm.s_pre + tm.K + 1;
+    int32_t* fpre = tm.s_pre + 2 * (tm.K + 1);
+    if (tm.K == 1) {
+        if (threadIdx.x == 0) {
+            bpre0[0] = 0;
+            bpre0[1] = int32_t(nb_local[0]);
+            bpre1[0] = 0;
+            bpre1[1] = int32_t(nb_local[1]);
+            fpre[0] = 0;
+            fpre[1] = 0;
+            fpre[2] = int32_t(live);
+        }
+        __syncthreads();
+    } else {
+        if (threadIdx.x == 0) {
+            int32_t* cnt = tm.counts + int64_t(tm.base + 8u * uint32_t(tm.r)) * kCountWords;
+            cnt[0] = int32_t(nb_local[0]);
+            cnt[1] = int32_t(nb_local[1]);
+            cnt[2] = int32_t(nf_local[0]);
+            cnt[3] = int32_t(nf_local[1]);
+            cnt[4] = int32_t(live);
+        }
+        if (!team_sync(tm)) return false;   // every member's list and counts are visible
+        if (threadIdx.x == 0) {
+            int32_t b0 = 0, b1 = 0, f0 = 0, f1 = 0, lv = 0;
+            for (int j = 0; j < tm.K; ++j) {
+                const int32_t* cnt = tm.counts + int64_t(tm.base + 8u * uint32_t(j)) * kCountWords;
+                bpre0[j] = b0;
+                bpre1[j] = b1;
+                b0 += cnt[0];
+                b1 += cnt[1];
+                if (j < tm.r) {
+                    f0 += cnt[2];
+                    f1 += cnt[3];
+                }
+                lv += cnt[4];
+            }
+            bpre0[tm.K] = b0;
+            bpre1[tm.K] = b1;
+            fpre[0] = f0;
+            fpre[1] = f1;
+            fpre[2] = lv;
+        }
+        __syncthreads();
+    }
+    *live_out = uint32_t(fpre[2]);
 
     // ---- C: re-arm claims, breed into free slots, starve
+#pragma unroll
     for (int s = 0; s < 2; ++s) {
-        uint32_t base_rank = 0;
-        for (int32_t c0 = 0; c0 < v.cap[s]; c0 += chunk) {
+        const int32_t* bpre = s ? bpre1 : bpre0;
+        const uint32_t nb = uint32_t(bpre[tm.K]);
+        const int32_t list_off = s ? per0 : 0;
+        uint32_t base_rank = uint32_t(fpre[s]);
+        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < v.cap[s] ? v.al[s][i] : 1;
+                al[k] = i < hi[s] ? v.al[s][i] : 1;
             }
             bool fr[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                fr[k] = i < v.cap[s] && (al[k] == 0 || al[k] == 2);
-                if (i >= v.cap[s] || al[k] == 0) continue;
+                fr[k] = i < hi[s] && (al[k] == 0 || al[k] == 2);
+                if (i >= hi[s] || al[k] == 0) continue;
                 // this agent posted claims in A: reset them
                 const int32_t x = v.x[s][i], y = v.y[s][i];
                 if (!on_grid(v, x, y)) continue;
@@ -264,8 +404,10 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
                 const uint32_t j = base_rank + rank[k];
-                if (fr[k] && j < nb[s]) {
-                    const int32_t p = breeders[(s ? v.cap[0] : 0) + j];
+                if (fr[k] && j < nb) {
+                    int q = 0;   // the member whose list holds breeder j
+                    while (q + 1 < tm.K && uint32_t(bpre[q + 1]) <= j) ++q;
+                    const int32_t p = member_list(tm, q)[list_off + int32_t(j) - bpre[q]];
                     const int32_t ep = v.e[s][p];
                     const int32_t ec = ep >> 1;
                     v.x[s][i] = v.x[s][p];
@@ -273,79 +415,127 @@ __device__ void model_step(const ModelView& v, uint32_t t, int32_t* breeders, ui
                     v.e[s][i] = ec;
                     v.e[s][p] = ep - ec;
                     v.al[s][i] = 1;
-                } else if (i < v.cap[s]) {
-                    if (al[k] == 2) {
-                        v.al[s][i] = 0;
-                    } else if (al[k] != 0 && v.e[s][i] < 0) {
-                        // a breeder's energy stays positive, so no slot read by a child dies here
-                        v.al[s][i] = 0;
-                    }
+                } else if (i < hi[s]) {
+                    // a breeder's energy stays positive, so no slot read by a child dies
+                    // here, whichever of its two values another member's child leaves
+                    if (al[k] == 2 || (al[k] != 0 && v.e[s][i] < 0)) v.al[s][i] = 0;
                 }
             }
             base_rank += tot;
         }
     }
-    __syncthreads();
+    // births, deaths and re-armed claims are visible to the next step
+    return team_sync(tm);
 }
 
+__device__ ModelView view_of(const BatchArgs& a, const abm_model_desc* d) {
+    ModelView v;
+    v.W = d->W;
+    v.H = d->H;
+    v.R = d->R;
+    v.gain[0] = d->gain_s;
+    v.gain[1] = d->gain_w;
+    v.T[0] = d->T_s;
+    v.T[1] = d->T_w;
+    v.seed = d->seed;
+    v.cap[0] = int32_t(d->cap_s);
+    v.cap[1] = int32_t(d->cap_w);
+    v.ready = a.ready + d->cell_off;
+    v.claims = a.claims + 3 * d->cell_off;
+    v.x[0] = a.sx + d->sheep_off;
+    v.y[0] = a.sy + d->sheep_off;
+    v.e[0] = a.se + d->sheep_off;
+    v.al[0] = a.sa + d->sheep_off;
+    v.x[1] = a.wx + d->wolf_off;
+    v.y[1] = a.wy + d->wolf_off;
+    v.e[1] = a.we + d->wolf_off;
+    v.al[1] = a.wa + d->wolf_off;
+    return v;
+}
+
+// Runs model m's pending steps (at most max_steps) with team tm; member 0
+// updates the descriptor.  False if a team barrier failed.
+template <int ITEMS>
+__device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds) {
+    abm_model_desc* d = a.models + m;
+    if (d->cap_s + d->cap_w > a.scratch_stride) {
+        // the descriptor does not fit the breeder list (max_cap too small):
+        // leave the model untouched and report it
+        if (threadIdx.x == 0 && tm.r == 0) st_agent(tm.err, 1ull);
+        return true;
+    }
+    const ModelView v = view_of(a, d);
+    const int32_t t0 = d->step;
+    int32_t t1 = d->steps_target;
+    if (t1 - t0 > a.max_steps) t1 = t0 + a.max_steps;
+    uint64_t updates = 0;
+    for (int32_t t = t0; t < t1; ++t) {
+        uint32_t live;
+        if (!model_step<ITEMS>(v, uint32_t(t), tm, lds, &live)) return false;
+        updates += live;
+    }
+    if (threadIdx.x == 0 && tm.r == 0 && t1 > t0) {
+        d->step = t1;
+        d->updates += int64_t(updates);
+    }
+    return true;
+}
+
+// Workgroups [0, team_wgs) form teams of team_k members and take models
+// order[0, n_team) from queue 0; once that queue is empty they work alone like
+// the other workgroups, which take order[n_team, n_models) from queue 1.
 template <int ITEMS>
 __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
     __shared__ uint32_t lds[16];
-    __shared__ int32_t s_model;
-    int32_t* breeders = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
+    __shared__ int32_t s_pre[2 * (kMaxTeam + 1) + 3];
+    __shared__ int32_t s_ok, s_model;
+    const uint32_t b = blockIdx.x;
+    Team tm;
+    tm.gen = 0;
+    tm.scratch = a.scratch;
+    tm.stride = a.scratch_stride;
+    tm.counts = a.team_counts;
+    tm.err = a.err;
+    tm.s_pre = s_pre;
+    tm.s_ok = &s_ok;
+    if (b < a.team_wgs) {
+        const uint32_t xcd = b % 8, idx = b / 8;
+        const uint32_t team = xcd + 8 * (idx / a.team_k);
+        tm.K = int(a.team_k);
+        tm.r = int(idx % a.team_k);
+        tm.base = xcd + 8 * (idx - uint32_t(tm.r));
+        tm.ctr = a.team_ctr + team;
+        int32_t* mailbox = a.team_mail + team;
+        for (;;) {
+            if (threadIdx.x == 0 && tm.r == 0) {
+                const uint32_t q = atomicAdd(a.queue + 0, 1u);
+                __hip_atomic_store(mailbox, q < uint32_t(a.n_team) ? a.order[q] : -1,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!team_sync(tm)) return;
+            if (threadIdx.x == 0)
+                s_model = __hip_atomic_load(mailbox, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // every member has read the mailbox before the leader writes it again
+            if (!team_sync(tm)) return;
+            const int32_t m = s_model;
+            if (m < 0) break;
+            if (!run_model<ITEMS>(a, m, tm, lds)) return;
+        }
+    }
+    tm.K = 1;
+    tm.r = 0;
+    tm.base = b;
+    tm.ctr = nullptr;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t q = atomicAdd(a.queue, 1u);
+            const uint32_t q = uint32_t(a.n_team) + atomicAdd(a.queue + 1, 1u);
             s_model = q < uint32_t(a.n_models) ? a.order[q] : -1;
         }
         __syncthreads();
         const int32_t m = s_model;
         __syncthreads();
         if (m < 0) break;
-        abm_model_desc* d = a.models + m;
-        if (d->cap_s + d->cap_w > a.scratch_stride) {
-            // the descriptor does not fit the breeder list (max_cap too small):
-            // leave the model untouched and report it
-            if (threadIdx.x == 0)
-                __hip_atomic_store(reinterpret_cast<uint64_t*>(a.queue) + kHdrError, 1ull,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            continue;
-        }
-        ModelView v;
-        v.W = d->W;
-        v.H = d->H;
-        v.R = d->R;
-        v.gain[0] = d->gain_s;
-        v.gain[1] = d->gain_w;
-        v.T[0] = d->T_s;
-        v.T[1] = d->T_w;
-        v.seed = d->seed;
-        v.cap[0] = int32_t(d->cap_s);
-        v.cap[1] = int32_t(d->cap_w);
-        v.ready = a.ready + d->cell_off;
-        v.claims = a.claims + 3 * d->cell_off;
-        v.x[0] = a.sx + d->sheep_off;
-        v.y[0] = a.sy + d->sheep_off;
-        v.e[0] = a.se + d->sheep_off;
-        v.al[0] = a.sa + d->sheep_off;
-        v.x[1] = a.wx + d->wolf_off;
-        v.y[1] = a.wy + d->wolf_off;
-        v.e[1] = a.we + d->wolf_off;
-        v.al[1] = a.wa + d->wolf_off;
-        const int32_t t0 = d->step;
-        int32_t t1 = d->steps_target;
-        if (t1 - t0 > a.max_steps) t1 = t0 + a.max_steps;
-        uint64_t updates = 0;
-        for (int32_t t = t0; t < t1; ++t) {
-            uint32_t live;
-            model_step<ITEMS>(v, uint32_t(t), breeders, lds, &live);
-            updates += live;
-        }
-        if (threadIdx.x == 0 && t1 > t0) {
-            d->step = t1;
-            d->updates += int64_t(updates);
-        }
-        __syncthreads();
+        run_model<ITEMS>(a, m, tm, lds);
     }
 }
 
@@ -422,8 +612,11 @@ __global__ __launch_bounds__(256) void k_batched_count(abm_model_desc* models, c
     }
 }
 
-__global__ void k_reset_queue(uint32_t* q) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *reinterpret_cast<uint64_t*>(q) = 0;
+// Clears the queue counters and the team barrier counters of a run.
+__global__ void k_reset_queue(uint32_t* q, uint32_t* team_ctr, int32_t n_teams) {
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *reinterpret_cast<uint64_t*>(q) = 0;
+    if (i < n_teams) team_ctr[i] = 0;
 }
 
 int check_batch(const abm_batch* b) {
@@ -446,9 +639,17 @@ int check_batch(const abm_batch* b) {
 
 using namespace abm;
 
+// Workspace of a batched run: a 256-byte header (queue counters; error word at
+// byte 248), the team area (barrier counter and model mailbox per team, member
+// counts per workgroup) and one breeder list (2 * max_cap ints) per workgroup.
+constexpr int64_t kTeamAreaWords = int64_t(kMaxWorkgroups) * (2 + kCountWords);
+
 extern "C" size_t abm_batched_workspace_bytes(int64_t max_cap, int32_t n_workgroups) {
-    if (max_cap < 1 || n_workgroups < 1) return 0;
-    return size_t(kHeaderBytes) + size_t(n_workgroups) * size_t(2 * max_cap) * 4 + 256;
+    if (max_cap < 1 || max_cap > (int64_t(1) << 30) || n_workgroups < 1 ||
+        n_workgroups > kMaxWorkgroups)
+        return 0;
+    return size_t(kHeaderBytes) + size_t(4 * kTeamAreaWords) +
+           size_t(n_workgroups) * size_t(2 * max_cap) * 4 + 256;
 }
 
 extern "C" int abm_predation_batched_init(const abm_batch* b, void* stream) {
@@ -489,9 +690,34 @@ extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* orde
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess)
         return launch_status("predation_run_batched: device query");
     if (per_cu < 1) per_cu = 1;
-    int grid = n_cu * per_cu;
-    if (tune && tune->workgroups > 0 && tune->workgroups < grid) grid = tune->workgroups;
-    if (grid > b->n_models) grid = b->n_models;
+    int resident = n_cu * per_cu;
+    if (tune && tune->workgroups > 0 && tune->workgroups < resident) resident = tune->workgroups;
+    if (resident > kMaxWorkgroups) resident = kMaxWorkgroups;
+    // teams: order[0, n_team) is run by teams of K workgroups, formed from the
+    // first team_wgs workgroups (a multiple of 8 K)
+    const int K = tune && tune->team_size > 1 ? tune->team_size : 1;
+    int n_team = K > 1 && tune ? tune->team_models : 0;
+    if (K > kMaxTeam) return fail(ABM_E_INVALID, "team_size must be at most 16");
+    if (n_team < 0 || n_team > b->n_models)
+        return fail(ABM_E_INVALID, "team_models must be in [0, n_models]");
+    int team_wgs = 0;
+    if (n_team > 0) {
+        const int unit = 8 * K;
+        const int fit = resident / unit * unit;
+        if (fit == 0) {
+            set_error("teams of %d need %d resident workgroups, %d are available", K, unit,
+                      resident);
+            return ABM_E_INVALID;
+        }
+        team_wgs = tune->team_workgroups > 0 ? tune->team_workgroups
+                                             : (n_team * K + unit - 1) / unit * unit;
+        if (team_wgs % unit != 0)
+            return fail(ABM_E_INVALID, "team_workgroups must be a multiple of 8 * team_size");
+        if (team_wgs > fit) team_wgs = fit;
+    }
+    int grid = resident - team_wgs;
+    if (grid > b->n_models - n_team) grid = b->n_models - n_team;
+    grid += team_wgs;
     const size_t need = abm_batched_workspace_bytes(b->max_cap, grid);
     if (!ws || ws_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -515,10 +741,20 @@ extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* orde
     a.wy = b->wolves.y;
     a.we = b->wolves.e;
     a.wa = b->wolves.alive;
-    a.queue = reinterpret_cast<uint32_t*>(ws);
-    a.scratch = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + kHeaderBytes);
+    char* base = static_cast<char*>(ws);
+    a.queue = reinterpret_cast<uint32_t*>(base);
+    a.err = reinterpret_cast<uint64_t*>(base + kHeaderBytes - 8);
+    a.team_ctr = reinterpret_cast<uint32_t*>(base + kHeaderBytes);
+    a.team_mail = reinterpret_cast<int32_t*>(a.team_ctr + kMaxWorkgroups);
+    a.team_counts = a.team_mail + kMaxWorkgroups;
+    a.scratch = reinterpret_cast<int32_t*>(base + kHeaderBytes + 4 * kTeamAreaWords);
     a.scratch_stride = 2 * b->max_cap;
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, st, a.queue);
+    a.n_team = n_team;
+    a.team_k = uint32_t(K);
+    a.team_wgs = uint32_t(team_wgs);
+    const int n_teams = team_wgs / K;
+    hipLaunchKernelGGL(k_reset_queue, dim3((n_teams + 255) / 256 + 1), dim3(256), 0, st, a.queue,
+                       a.team_ctr, n_teams);
     switch (items) {
         case 1: hipLaunchKernelGGL(k_batched_run<1>, dim3(grid), dim3(block), 0, st, a); break;
         case 2: hipLaunchKernelGGL(k_batched_run<2>, dim3(grid), dim3(block), 0, st, a); break;

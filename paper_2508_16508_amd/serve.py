@@ -236,7 +236,7 @@ class GpuRunner:
 
     def __init__(self, cell_capacity, sheep_capacity, wolf_capacity, max_active=4096,
                  block_threads=512, items=4, device="cuda", keep_results=False,
-                 max_model_cap=None):
+                 max_model_cap=None, team_size=1, team_min_size=1 << 18):
         import torch
 
         import paper_2508_16508_amd as abm
@@ -253,6 +253,8 @@ class GpuRunner:
         self.init_desc = torch.zeros(max_active * self.desc_size, dtype=torch.uint8, device=device)
         self.order = torch.zeros(max_active, dtype=torch.int32, device=device)
         self.block_threads, self.items = block_threads, items
+        # models of at least team_min_size cells plus slots run on teams of workgroups
+        self.team_size, self.team_min_size = team_size, team_min_size
         props = torch.cuda.get_device_properties(self.ready.device)
         self.workgroups = props.multi_processor_count * max(1, 2048 // block_threads)
         # breeder scratch per workgroup is sized by the largest single model
@@ -303,7 +305,8 @@ class GpuRunner:
         order = np.argsort(-np.asarray(size), kind="stable").astype(np.int32)
         self.order[:n].copy_(torch.from_numpy(order))
         b = self._batch(self.desc, n)
-        t = abm.Tuning(self.block_threads, self.workgroups, self.items)
+        n_team = sum(1 for v in size if v >= self.team_min_size) if self.team_size > 1 else 0
+        t = abm.Tuning(self.block_threads, self.workgroups, self.items, self.team_size, n_team, 0)
         abm._check(abm.lib().abm_predation_run_batched(C.byref(b), abm._p(self.order), 1 << 30,
                                                        C.byref(t), abm._p(self.ws),
                                                        self.ws.numel(), abm._stream()))

@@ -146,3 +146,126 @@ def test_autotuner_picks_a_candidate_and_caches_it(abm, tmp_path):
     assert set(first["timings_ms"]) == {"256x2", "512x4"}
     again = autotune_batched(make, "test", steps=3, candidates=cands, cache_path=path)
     assert again["cached"] and again["block_threads"] == first["block_threads"]
+
+
+def _team_models(seed):
+    """Big models (split over a team) and small ones (one workgroup each):
+    capacities below, at and above the team size, a species with no agents,
+    a species larger than the grid, a 1-row torus."""
+    g = np.random.default_rng(seed)
+    kws = [dict(W=120, H=100, seed=int(g.integers(0, 2 ** 32)), cap_s=4800, cap_w=1200,
+                n_s0=1200, n_w0=300),
+           dict(W=200, H=90, seed=int(g.integers(0, 2 ** 32)), cap_s=20000, cap_w=3, n_s0=1800,
+                n_w0=3, T_w=2 ** 31 - 1),
+           dict(W=150, H=1, seed=int(g.integers(0, 2 ** 32)), cap_s=7000, cap_w=7000, n_s0=15,
+                n_w0=4, R=3),
+           dict(W=110, H=110, seed=int(g.integers(0, 2 ** 32)), cap_s=5000, cap_w=1, n_s0=900,
+                n_w0=0),
+           dict(W=100, H=100, seed=int(g.integers(0, 2 ** 32)), cap_s=12000, cap_w=2500,
+                n_s0=3000, n_w0=800, T_s=2 ** 30, T_w=2 ** 30)]
+    kws += _mixed_models(seed + 1, 12)
+    return kws
+
+
+@pytest.mark.parametrize("K,block,items", [(2, 256, 1), (4, 512, 4), (8, 256, 2), (16, 512, 4)])
+def test_teams_match_models_alone(abm, orc, K, block, items):
+    """Models of at least 6000 cells plus slots are advanced by teams of K
+    workgroups (three team barriers per step), the rest by one workgroup; every
+    model must match the oracle run alone, over three launches."""
+    kws = _team_models(K)
+    targets = [40, 33, 40, 12, 40] + [int(t) for t in np.random.default_rng(K).integers(0, 41, 12)]
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], targets,
+                                 block_threads=block, items=items, team_size=K,
+                                 team_min_size=6000)
+    assert batch.team_models() == 5
+    batch.init()
+    for _ in range(3):
+        batch.run(14)
+    torch.cuda.synchronize()
+    assert abm.workspace_error(batch.ws) == 0
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, min(targets[m], 42), cd)
+
+
+def test_team_equals_one_workgroup_on_a_large_model(abm):
+    """A 1024x1024 model of the served-trace recipe (sheep = cells/10, wolves =
+    cells/40, capacities 4x), 30 steps by a team of 16 and by one workgroup:
+    identical bytes."""
+    L = 1024
+    kw = dict(W=L, H=L, seed=77, cap_s=4 * (L * L // 10), cap_w=4 * (L * L // 40),
+              n_s0=L * L // 10, n_w0=L * L // 40)
+    out = []
+    for k in (16, 1):
+        b = abm.BatchedPredation([abm.predation_params(**kw)], 30, team_size=k, team_min_size=1)
+        b.init()
+        b.run(30)
+        torch.cuda.synchronize()
+        assert abm.workspace_error(b.ws) == 0
+        out.append((b.grass_countdown(), b.sheep, b.wolves, b.descriptors()[0]))
+    (g0, s0, w0, d0), (g1, s1, w1, d1) = out
+    assert torch.equal(g0, g1)
+    for f in FIELDS:
+        assert torch.equal(s0[f], s1[f]) and torch.equal(w0[f], w1[f])
+    assert (d0.step, d0.updates, d0.live_s, d0.live_w) == (d1.step, d1.updates, d1.live_s,
+                                                           d1.live_w)
+
+
+def test_team_launch_rejects_bad_tuning(abm):
+    kw = dict(W=64, H=64, seed=1)
+    b = abm.BatchedPredation([abm.predation_params(**kw)] * 2, 5, team_size=2, team_min_size=1)
+    b.init()
+    with pytest.raises(abm.AbmError, match="team_size"):
+        b.run(5, team_size=17)
+    with pytest.raises(abm.AbmError, match="resident"):
+        b.run(5, workgroups=15)                      # teams of 2 need 16 workgroups
+    with pytest.raises(abm.AbmError, match="multiple"):
+        b.run(5, team_workgroups=24)
+    b.run(5, workgroups=16)
+    d = b.descriptors()
+    assert d[0].step == 5 and d[1].step == 5
+
+
+@pytest.mark.parametrize("team_size", [1, 2])
+def test_resume_from_an_edited_state(abm, orc, team_size):
+    """Between launches, agents are killed in low slots and placed in the
+    highest slots: the next launch finds every live agent (it derives the
+    high-water mark of each species from the state) and matches the oracle run
+    from the edited state."""
+    kws = [dict(W=48, H=40, seed=3, cap_s=3000, cap_w=900, n_s0=300, n_w0=80),
+           dict(W=30, H=30, seed=9, cap_s=1000, cap_w=400, n_s0=100, n_w0=30)]
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 40,
+                                 team_size=team_size, team_min_size=1)
+    batch.init()
+    batch.run(10)
+    g = np.random.default_rng(team_size)
+    cd = batch.grass_countdown()
+    starts = []
+    for m, kw in enumerate(kws):
+        grass, sheep, wolves = batch.model_state(m, cd)
+        host = {}
+        for name, sp, cap in (("sheep", sheep, kw["cap_s"]), ("wolves", wolves, kw["cap_w"])):
+            arr = {f: _host(sp[f]).copy() for f in FIELDS}
+            live = np.flatnonzero(arr["alive"])
+            arr["alive"][live[g.random(live.size) < 0.3]] = 0
+            top = np.arange(cap - 5, cap)
+            arr["alive"][top] = 1
+            arr["x"][top] = g.integers(0, kw["W"], 5)
+            arr["y"][top] = g.integers(0, kw["H"], 5)
+            arr["e"][top] = g.integers(1, 20, 5)
+            for f in FIELDS:
+                sp[f].copy_(torch.from_numpy(arr[f]))
+            host[name] = arr
+        starts.append(orc.PredState(_host(grass).copy(), host["sheep"], host["wolves"], 10))
+    torch.cuda.synchronize()
+    batch.run(30)
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        S = starts[m]
+        orc.predation_run(orc.pred_params(**kw), S, 30)
+        grass, sheep, wolves = batch.model_state(m, cd)
+        assert np.array_equal(_host(grass), S.grass), m
+        for name, gsp, osp in (("sheep", sheep, S.sheep), ("wolves", wolves, S.wolves)):
+            for f in FIELDS:
+                assert np.array_equal(_host(gsp[f]), osp[f]), (m, name, f)
+        assert batch.descriptors()[m].step == 40

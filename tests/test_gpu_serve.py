@@ -10,7 +10,9 @@ from paper_2508_16508_amd import serve as S
 pytestmark = pytest.mark.gpu
 
 
-def test_each_result_same_alone_and_in_the_mix(abm, orc):
+@pytest.mark.parametrize("team_size", [1, 4])
+def test_each_result_same_alone_and_in_the_mix(abm, orc, team_size):
+    """team_size 4: models of at least 1200 cells plus slots run on teams."""
     g = np.random.default_rng(11)
     reqs = []
     t = 0.0
@@ -20,7 +22,8 @@ def test_each_result_same_alone_and_in_the_mix(abm, orc):
         steps = int(g.integers(5, 80))
         reqs.append(S.Request(i, t, side, steps, int(g.integers(0, 2 ** 32))))
     cells = 6 * 40 * 40          # room for only a handful of models at once: requests queue
-    runner = S.GpuRunner(cells, cells, cells // 2, keep_results=True)
+    runner = S.GpuRunner(cells, cells, cells // 2, keep_results=True, team_size=team_size,
+                         team_min_size=1200)
     sch = S.Scheduler(runner, cells, cells, cells // 2, slot_step_budget=4000)
     rep = sch.serve(reqs)
     summ = rep.summary()
