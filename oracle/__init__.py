@@ -45,6 +45,7 @@ class PredParams(C.Structure):
         ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
         ("cap_s", C.c_int64), ("cap_w", C.c_int64),
         ("n_s0", C.c_int64), ("n_w0", C.c_int64),
+        ("multi_prey", C.c_int32),
     ]
 
 
@@ -235,8 +236,9 @@ T_WOLF = 214748364
 
 
 def pred_params(W=64, H=64, R=30, gain_s=4, gain_w=20, T_s=T_SHEEP, T_w=T_WOLF, seed=0,
-                cap_s=4096, cap_w=1024, n_s0=400, n_w0=100) -> PredParams:
-    return PredParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0)
+                cap_s=4096, cap_w=1024, n_s0=400, n_w0=100, multi_prey=0) -> PredParams:
+    return PredParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0,
+                      multi_prey)
 
 
 @dataclass

@@ -259,6 +259,7 @@ typedef struct {
     uint32_t seed;
     int64_t cap_s, cap_w; /* slot capacities */
     int64_t n_s0, n_w0;   /* initial live counts */
+    int32_t multi_prey;   /* 0: one prey per cell; 1: every wolf of a cell may eat (see eat) */
 } orc_pred_params;
 
 typedef struct { int32_t *x, *y, *e, *alive; } orc_species;
@@ -392,6 +393,68 @@ ORC_API void orc_pred_move(const orc_pred_params* P, orc_pred_state* S)
  * Then prey: on every cell holding both live sheep and live wolves, the
  * lowest-key sheep is eaten by the lowest-key wolf (energy += gain_w).  So at
  * most one grass and one sheep are consumed per cell per step. */
+/* Ascending order of packed keys (the low 32 bits are the slot, so no two
+ * keys of one species are equal). */
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Prey with several matches per cell: on every cell, the live sheep are put
+ * in ascending order of their prey keys and the live wolves in ascending
+ * order of their eat keys, and for j < min(#sheep, #wolves) the j-th wolf
+ * eats the j-th sheep (the sheep dies, the wolf gains gain_w).  With at most
+ * one wolf or one sheep per cell this is the one-prey rule.  This is the
+ * rank-and-match of the toy task (Sec. 4, Alg. 1) applied per cell, with
+ * cells as the groups.  Returns the number of sheep eaten. */
+static int64_t eat_prey_multi(const orc_pred_params* P, orc_pred_state* S)
+{
+    const uint32_t t = S->step;
+    const int64_t G = (int64_t)P->W * P->H;
+    int64_t* off_s = (int64_t*)calloc((size_t)G + 1, sizeof(int64_t));
+    int64_t* off_w = (int64_t*)calloc((size_t)G + 1, sizeof(int64_t));
+    int64_t* fill_s = (int64_t*)calloc((size_t)G, sizeof(int64_t));
+    int64_t* fill_w = (int64_t*)calloc((size_t)G, sizeof(int64_t));
+    uint64_t* ks = (uint64_t*)malloc((size_t)(P->cap_s > 0 ? P->cap_s : 1) * sizeof(uint64_t));
+    uint64_t* kw = (uint64_t*)malloc((size_t)(P->cap_w > 0 ? P->cap_w : 1) * sizeof(uint64_t));
+    int64_t eaten = 0;
+
+    /* bucket the live agents of each species by cell */
+    for (int64_t i = 0; i < P->cap_s; ++i)
+        if (S->sheep.alive[i]) off_s[(int64_t)S->sheep.y[i] * P->W + S->sheep.x[i] + 1]++;
+    for (int64_t j = 0; j < P->cap_w; ++j)
+        if (S->wolves.alive[j]) off_w[(int64_t)S->wolves.y[j] * P->W + S->wolves.x[j] + 1]++;
+    for (int64_t c = 0; c < G; ++c) { off_s[c + 1] += off_s[c]; off_w[c + 1] += off_w[c]; }
+    for (int64_t i = 0; i < P->cap_s; ++i) {
+        if (!S->sheep.alive[i]) continue;
+        int64_t c = (int64_t)S->sheep.y[i] * P->W + S->sheep.x[i];
+        ks[off_s[c] + fill_s[c]++] = agent_key(P->seed, t, i, P_S_PREY_KEY);
+    }
+    for (int64_t j = 0; j < P->cap_w; ++j) {
+        if (!S->wolves.alive[j]) continue;
+        int64_t c = (int64_t)S->wolves.y[j] * P->W + S->wolves.x[j];
+        kw[off_w[c] + fill_w[c]++] = agent_key(P->seed, t, j, P_W_EAT_KEY);
+    }
+    /* per cell: order both groups by key and pair them rank by rank */
+    for (int64_t c = 0; c < G; ++c) {
+        int64_t n_s = off_s[c + 1] - off_s[c], n_w = off_w[c + 1] - off_w[c];
+        int64_t m = n_s < n_w ? n_s : n_w;
+        if (m == 0) continue;
+        qsort(ks + off_s[c], (size_t)n_s, sizeof(uint64_t), cmp_u64);
+        qsort(kw + off_w[c], (size_t)n_w, sizeof(uint64_t), cmp_u64);
+        for (int64_t r = 0; r < m; ++r) {
+            int64_t prey = (int64_t)(uint32_t)(ks[off_s[c] + r] & 0xFFFFFFFFULL);
+            int64_t wolf = (int64_t)(uint32_t)(kw[off_w[c] + r] & 0xFFFFFFFFULL);
+            S->sheep.alive[prey] = 0;
+            S->wolves.e[wolf] += P->gain_w;
+            ++eaten;
+        }
+    }
+    free(off_s); free(off_w); free(fill_s); free(fill_w); free(ks); free(kw);
+    return eaten;
+}
+
 ORC_API void orc_pred_eat(const orc_pred_params* P, orc_pred_state* S,
                           int64_t* grass_eaten, int64_t* sheep_eaten)
 {
@@ -417,6 +480,13 @@ ORC_API void orc_pred_eat(const orc_pred_params* P, orc_pred_state* S,
         ++ng;
     }
 
+    if (P->multi_prey) {
+        free(best); free(best2);
+        ns = eat_prey_multi(P, S);
+        if (grass_eaten) *grass_eaten = ng;
+        if (sheep_eaten) *sheep_eaten = ns;
+        return;
+    }
     for (int64_t c = 0; c < G; ++c) { best[c] = UINT64_MAX; best2[c] = UINT64_MAX; }
     for (int64_t i = 0; i < P->cap_s; ++i) {
         if (!S->sheep.alive[i]) continue;

@@ -2,8 +2,9 @@
 
 The expected states in ``predation_hand_1x1.txt`` and ``predation_hand_3x3.txt``
 were worked out by hand from these draws and the model rules (Sec. 5.1, with
-the step order move, eat, breed, die, regrow).  This script calls only the
-oracle's RNG (which is itself pinned to the published SplitMix64 vectors).
+the step order move, eat, breed, die, regrow); ``predation_multi_prey_1x1.txt``
+from the prey and eat keys of one step.  This script calls only the oracle's
+RNG (which is itself pinned to the published SplitMix64 vectors).
 
     python tests/golden/make_predation_draws.py
 """
@@ -44,6 +45,15 @@ def dump(seed, cells, cap_s, cap_w, steps):
                 print(f"t={t} wolf {i} {NAMES[p]} = {h}{extra}")
 
 
+def dump_keys(seed, step, n_s, n_w):
+    print(f"# seed={seed} step={step}")
+    for i in range(n_s):
+        print(f"t={step} sheep {i} S_PREY_KEY = {O.rng(seed, step, i, 0x15)}")
+    for j in range(n_w):
+        print(f"t={step} wolf {j} W_EAT_KEY = {O.rng(seed, step, j, 0x24)}")
+
+
 if __name__ == "__main__":
     dump(5, 1, 4, 2, 2)
     dump(11, 9, 3, 3, 2)
+    dump_keys(21, 7, 4, 3)

@@ -110,9 +110,17 @@ def _check_eat(orc, P, before, after, t, ng, ns):
             exp_grass[c] = P.R
             n_grass += 1
     for c, sheep in by_cell_s.items():
-        if c in by_cell_w:
-            prey = min(sheep, key=lambda i: _key(orc, P, t, i, 0x15))
-            wolf = min(by_cell_w[c], key=lambda j: _key(orc, P, t, j, 0x24))
+        if c not in by_cell_w:
+            continue
+        if P.multi_prey:
+            # the r-th sheep (by prey key) of the cell is eaten by its r-th wolf (by eat key)
+            prey_order = sorted(sheep, key=lambda i: _key(orc, P, t, i, 0x15))
+            wolf_order = sorted(by_cell_w[c], key=lambda j: _key(orc, P, t, j, 0x24))
+            pairs = list(zip(prey_order, wolf_order))
+        else:
+            pairs = [(min(sheep, key=lambda i: _key(orc, P, t, i, 0x15)),
+                      min(by_cell_w[c], key=lambda j: _key(orc, P, t, j, 0x24)))]
+        for prey, wolf in pairs:
             exp_alive_s[prey] = 0
             exp_e_w[wolf] += P.gain_w
             n_prey += 1
@@ -122,7 +130,9 @@ def _check_eat(orc, P, before, after, t, ng, ns):
     assert np.array_equal(after.grass, exp_grass)
     for f in ("x", "y"):
         assert np.array_equal(sa[f], sb[f]) and np.array_equal(wa[f], wb[f])
-    assert ng <= G and ns <= G
+    assert ng <= G and ns <= min(live_s.size, live_w.size)
+    if not P.multi_prey:
+        assert ns <= G
 
 
 def _check_breed(orc, P, before, after, t, bs, bw):
@@ -201,16 +211,18 @@ def _phase_checked_step(orc, P, S):
                 births_s=bs, births_w=bw, starved_s=ss, starved_w=sw)
 
 
+@pytest.mark.parametrize("multi_prey", [0, 1])
 @pytest.mark.parametrize("W,H,cap_s,cap_w,n_s0,n_w0,seeds,steps", [
     (1, 1, 6, 4, 3, 2, range(0, 40), 6),      # every agent on one cell: all conflicts
     (2, 1, 6, 4, 4, 2, range(40, 70), 6),
     (3, 3, 8, 6, 5, 3, range(70, 90), 8),
     (8, 8, 64, 16, 20, 6, range(90, 94), 12),
 ])
-def test_phase_invariants_tiny(orc, W, H, cap_s, cap_w, n_s0, n_w0, seeds, steps):
+def test_phase_invariants_tiny(orc, W, H, cap_s, cap_w, n_s0, n_w0, seeds, steps, multi_prey):
     for seed in seeds:
         P = orc.pred_params(W=W, H=H, R=3, T_s=2**31, T_w=2**31, seed=seed,
-                            cap_s=cap_s, cap_w=cap_w, n_s0=n_s0, n_w0=n_w0)
+                            cap_s=cap_s, cap_w=cap_w, n_s0=n_s0, n_w0=n_w0,
+                            multi_prey=multi_prey)
         S = orc.predation_init(P)
         ref = S.copy()
         for _ in range(steps):
@@ -310,3 +322,70 @@ def test_small_workload_population_oscillates(orc):
         persisted += live_s[-1] > 0
         assert max(live_s) > min(live_s)
     assert persisted >= 3
+
+
+def _eat_both_ways(orc, P, S):
+    a, b = S.copy(), S.copy()
+    P1 = orc.pred_params(**{f: getattr(P, f) for f, _ in P._fields_ if f != "multi_prey"},
+                         multi_prey=1)
+    ra = orc.pred_eat(P, a)
+    rb = orc.pred_eat(P1, b)
+    return a, b, ra, rb
+
+
+def test_multi_prey_reduces_to_one_prey_rule(orc):
+    """With at most one wolf or at most one sheep on every cell, pairing by rank
+    eats exactly what the one-prey rule eats (the rule the rest of the model,
+    and the GPU path, is pinned on)."""
+    g = np.random.default_rng(5)
+    checked = 0
+    for trial in range(300):
+        P = orc.pred_params(W=6, H=5, seed=int(g.integers(0, 2**32)), cap_s=40, cap_w=12,
+                            n_s0=0, n_w0=0)
+        S = orc.predation_init(P)
+        S.step = int(g.integers(0, 1000))
+        ns, nw = int(g.integers(0, 40)), int(g.integers(0, 12))
+        cells_w = g.choice(30, size=nw, replace=False) if trial % 2 else g.integers(0, 30, nw)
+        cells_s = g.integers(0, 30, ns) if trial % 2 else g.choice(30, size=min(ns, 30), replace=False)
+        for sp, cells in (("sheep", cells_s), ("wolves", cells_w)):
+            d = getattr(S, sp)
+            for i, c in enumerate(cells):
+                d["x"][i], d["y"][i], d["alive"][i], d["e"][i] = c % 6, c // 6, 1, 5
+        a, b, ra, rb = _eat_both_ways(orc, P, S)
+        assert ra == rb
+        for sp in SPECIES:
+            for f in FIELDS:
+                assert np.array_equal(getattr(a, sp)[f], getattr(b, sp)[f])
+        checked += 1
+    assert checked == 300
+
+
+def test_multi_prey_worked_cell(orc):
+    """One cell, keys ordered by hand in tests/golden/predation_multi_prey_1x1.txt:
+    (a) four sheep and three wolves, (b) two sheep and three wolves."""
+    meta, exp = {}, {}
+    for line in open(golden_path("predation_multi_prey_1x1.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        key, val = line.split(":", 1)
+        if key == "params":
+            meta = {k: int(v) for k, v in (t.split("=") for t in val.split())}
+        else:
+            exp[key] = [int(v) for v in val.split()]
+    P = orc.pred_params(**meta)
+    for case, n_s, e_w in (("a", 4, [7, 7, 7]), ("b", 2, [7, 8, 9])):
+        S = orc.predation_init(P)
+        S.step = exp["step"][0]
+        for sp, n in (("sheep", n_s), ("wolves", 3)):
+            d = getattr(S, sp)
+            d["alive"][:] = 0
+            d["alive"][:n] = 1
+            d["x"][:] = 0
+            d["y"][:] = 0
+            d["e"][:n] = 7
+        S.wolves["e"][:3] = e_w
+        ng, ns = orc.pred_eat(P, S)
+        assert ns == min(n_s, 3), case
+        assert list(S.sheep["alive"]) == exp[f"{case}.sheep_alive_after"], case
+        assert list(S.wolves["e"]) == exp[f"{case}.wolf_e_after"], case
