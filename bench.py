@@ -379,6 +379,11 @@ def main():
                              n_w0=400_000, seed=0), 999,
             "2048x2048 torus, 1.6M sheep / 0.4M wolves in 2^24 / 2^22 slots, steps 1-999 "
             "after a warm-up step")
+        out["predation_large_multi_prey"] = predation_leg(
+            abm, torch, dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
+                             n_w0=400_000, seed=0, multi_prey=1), 999,
+            "2048x2048 torus as above with prey matched by rank within each cell (the r-th "
+            "wolf of a cell eats its r-th sheep), steps 1-999 after a warm-up step")
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()
     if args.served_seconds > 0:

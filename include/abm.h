@@ -169,7 +169,10 @@ ABM_API int abm_resolve_conflicts(int64_t n_claims, const int32_t* target, const
  *   eat    grass: on each grown cell holding live sheep, the sheep with the
  *          lowest key (draw << 32 | slot) eats (+gain_s, countdown = R);
  *          prey: on each cell holding live sheep and live wolves, the
- *          lowest-key sheep is eaten by the lowest-key wolf (+gain_w);
+ *          lowest-key sheep is eaten by the lowest-key wolf (+gain_w); with
+ *          multi_prey = 1, for every r below min(#sheep, #wolves) of the
+ *          cell the r-th sheep in key order is eaten by the r-th wolf in key
+ *          order (the rank-and-match of Sec. 4, Alg. 1, per cell);
  *   breed  live agents with energy > 0 and draw < T reproduce: the j-th
  *          breeder (ascending slot) puts a child on its own cell into the
  *          j-th lowest free slot; child energy e >> 1, parent keeps the rest;
@@ -187,6 +190,8 @@ typedef struct abm_predation_params {
     uint32_t seed;
     int64_t cap_s, cap_w;  /* slot capacities, 1 <= cap < 2^31 */
     int64_t n_s0, n_w0;    /* initial live agents (slots 0 .. n0-1), n0 <= cap */
+    int32_t multi_prey;    /* 0: one prey per cell; 1: prey matched by rank within a cell
+                              (abm_predation_step only; the batched form has the one-prey rule) */
 } abm_predation_params;
 
 typedef struct abm_species {

@@ -54,7 +54,7 @@ class PredationParams(C.Structure):
                 ("gain_s", C.c_int32), ("gain_w", C.c_int32),
                 ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
                 ("cap_s", C.c_int64), ("cap_w", C.c_int64),
-                ("n_s0", C.c_int64), ("n_w0", C.c_int64)]
+                ("n_s0", C.c_int64), ("n_w0", C.c_int64), ("multi_prey", C.c_int32)]
 
 
 class SpeciesPtrs(C.Structure):
@@ -414,10 +414,13 @@ class PredationModel:
 
 
 def predation_params(W=64, H=64, R=30, gain_s=4, gain_w=20, T_s=171798691, T_w=214748364,
-                     seed=0, cap_s=4096, cap_w=1024, n_s0=400, n_w0=100) -> PredationParams:
+                     seed=0, cap_s=4096, cap_w=1024, n_s0=400, n_w0=100,
+                     multi_prey=0) -> PredationParams:
     """Defaults: the small 64x64 workload (regrowth 30, gains 4 / 20,
-    reproduction 0.04 / 0.05 as floor(p * 2^32))."""
-    return PredationParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0)
+    reproduction 0.04 / 0.05 as floor(p * 2^32)).  multi_prey = 1: wolves and
+    sheep of a cell are matched by rank (one-model path only)."""
+    return PredationParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0,
+                           multi_prey)
 
 
 def predation_init(params, model: PredationModel | None = None, device="cuda", stream=None):
@@ -461,6 +464,8 @@ class BatchedPredation:
     def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4,
                  team_size=1, team_min_size=1 << 18):
         self.params = list(models)
+        if any(getattr(p, "multi_prey", 0) for p in self.params):
+            raise ValueError("the batched form implements the one-prey rule only (multi_prey = 0)")
         n = len(self.params)
         tgt = [steps_target] * n if isinstance(steps_target, int) else list(steps_target)
         self.n_models = n

@@ -17,6 +17,11 @@
 //                   rest; live agents with negative energy die.
 //   K4 regrow       every countdown above zero drops by one and the claim
 //                   tables are re-armed for the next step.
+// With multi_prey, K1 instead pushes every live sheep and wolf onto a list of
+// its cell (64-bit atomicExch on the prey / eater words, which then hold list
+// heads), and K1b, between K1 and K2, pairs the r-th wolf of each cell (eat
+// key order) with the r-th sheep (prey key order): the wolf gains, the sheep
+// is marked alive = 2 (eaten, still to take part in the grass rule of K2).
 // Pulling into the free slot (rather than the parent pushing into some later
 // tile) keeps every slot written by the thread that ranked it.
 #include <hip/hip_runtime.h>
@@ -70,6 +75,7 @@ struct StepArgs {
     int64_t* d_nb[2];     // breeder counts
     uint32_t tiles[2];
     uint32_t chain_off[2];  // start of each species' scan chain in the status words
+    int32_t multi;          // prey by rank within a cell (K1 builds lists, K1b matches)
 };
 
 __device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t n) {
@@ -174,6 +180,15 @@ __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
         a.sp[s].e[i] -= 1;
         const int64_t c = cell_of(x, y, a.W, a.H);
         if (c < 0) {
+        } else if (a.multi) {
+            // push slot i onto the list of its cell; the list ends at all-ones
+            if (s == 0 && a.grass[c] == 0)
+                atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c),
+                          (unsigned long long)agent_key(skey, i, kSheepGrassKey));
+            uint64_t* head = (s ? a.wclaim : a.sclaim) + c;
+            const uint64_t prev = atomicExch(reinterpret_cast<unsigned long long*>(head),
+                                             (unsigned long long)i);
+            a.blist[s][i] = int32_t(prev);   // all-ones -> -1
         } else if (s == 0) {
             if (a.grass[c] == 0)
                 atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c),
@@ -188,6 +203,36 @@ __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
     if (a.stats) {
         block_add(live_s, a.acc, kLiveS, lds);
         block_add(live_w, a.acc, kLiveW, lds);
+    }
+}
+
+// K1b (multi_prey): wolf j of cell c takes rank r among the wolves of c (eat
+// keys) and eats the sheep of rank r among the sheep of c (prey keys), if the
+// cell has that many.  Ranks are counted over the cell's lists; the lists of a
+// cell are short at the workloads' densities (a few agents), and the count is
+// quadratic in the sheep of one cell at worst.  Distinct wolves of a cell
+// have distinct ranks, so no sheep is taken twice.
+__global__ __launch_bounds__(kBlock) void k_prey_match(StepArgs a) {
+    const int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (j >= a.cap_w || a.sp[1].alive[j] == 0) return;
+    const int64_t c = cell_of(a.sp[1].x[j], a.sp[1].y[j], a.W, a.H);
+    if (c < 0) return;
+    const uint64_t skey = stream_key(a.seed, a.step);
+    const uint64_t my_key = agent_key(skey, j, kWolfEatKey);
+    uint32_t r = 0;
+    for (int32_t w = int32_t(a.wclaim[c]); w >= 0; w = a.blist[1][w])
+        r += agent_key(skey, w, kWolfEatKey) < my_key;
+    const int32_t first = int32_t(a.sclaim[c]);
+    for (int32_t q = first; q >= 0; q = a.blist[0][q]) {
+        const uint64_t kq = agent_key(skey, q, kSheepPreyKey);
+        uint32_t below = 0;
+        for (int32_t u = first; u >= 0; u = a.blist[0][u])
+            below += agent_key(skey, u, kSheepPreyKey) < kq;
+        if (below == r) {
+            a.sp[0].alive[q] = 2;
+            a.sp[1].e[j] += a.gain_w;
+            return;
+        }
     }
 }
 
@@ -231,14 +276,20 @@ __global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
                 a.grass[c] = a.R;
                 ++grass_eaten;
             }
-            if (a.wclaim[c] != kNoClaim && a.sclaim[c] == agent_key(skey, i, kSheepPreyKey)) {
+            const bool eaten =
+                a.multi ? sp.alive[i] == 2
+                        : (a.wclaim[c] != kNoClaim &&
+                           a.sclaim[c] == agent_key(skey, i, kSheepPreyKey));
+            if (eaten) {
                 sp.alive[i] = 0;
                 ++sheep_eaten;
                 continue;
             }
             f[k] = e > 0 && draw(skey, uint32_t(i), kSheepBreed) < a.T_s;
         } else {
-            if (a.sclaim[c] != kNoClaim && a.wclaim[c] == agent_key(skey, i, kWolfEatKey)) {
+            // (multi_prey: K1b has already added the gain)
+            if (!a.multi && a.sclaim[c] != kNoClaim &&
+                a.wclaim[c] == agent_key(skey, i, kWolfEatKey)) {
                 e += a.gain_w;
                 sp.e[i] = e;
             }
@@ -359,6 +410,8 @@ int check_params(const abm_predation_params* p) {
         return fail(ABM_E_INVALID, "cap_s + cap_w must be below 2^31");
     if (p->n_s0 < 0 || p->n_w0 < 0 || p->n_s0 > p->cap_s || p->n_w0 > p->cap_w)
         return fail(ABM_E_INVALID, "initial counts must be in [0, capacity]");
+    if (p->multi_prey != 0 && p->multi_prey != 1)
+        return fail(ABM_E_INVALID, "multi_prey must be 0 or 1");
     return ABM_OK;
 }
 
@@ -456,6 +509,7 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.tiles[1] = static_cast<uint32_t>(tiles_for(p->cap_w, kTile));
     a.chain_off[0] = 0;
     a.chain_off[1] = static_cast<uint32_t>(chain_words(a.tiles[0]));
+    a.multi = p->multi_prey;
 
     const dim3 cell_grid(static_cast<uint32_t>(tiles_for(G, kBlock)));
     const dim3 agent_grid(static_cast<uint32_t>(tiles_for(p->cap_s + p->cap_w, kBlock)));
@@ -473,6 +527,9 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
         hipLaunchKernelGGL(k_move_claim, agent_grid, dim3(kBlock), 0, st, a);
+        if (a.multi)
+            hipLaunchKernelGGL(k_prey_match, dim3(static_cast<uint32_t>(tiles_for(p->cap_w, kBlock))),
+                               dim3(kBlock), 0, st, a);
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_eat_breeders, scan_grid, dim3(kWaves * 64), 0, st, a);

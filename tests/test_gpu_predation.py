@@ -126,3 +126,62 @@ def test_large_workload(abm, orc):
     alive_s = int(_host(model.sheep["alive"]).sum())
     assert alive_s == st[n - 1][0] - st[n - 1][3] - st[n - 1][6] + st[n - 1][4]
     assert abm.workspace_error(model.ws) == 0
+
+
+# ---------------------------------------------------------------- multi-prey
+@pytest.mark.parametrize("seed", range(4))
+def test_multi_prey_small_workload_every_step(abm, orc, seed):
+    """multi_prey = 1 on the 64x64 workload: state and statistics after every
+    one of 200 steps."""
+    P, S, model = _pair(abm, orc, seed=seed, multi_prey=1)
+    stats = torch.zeros((1, 8), dtype=torch.int64, device="cuda")
+    for t in range(200):
+        exp = orc.predation_step(P, S)
+        model.run(1, stats)
+        got = dict(zip(abm.STAT_NAMES, (int(v) for v in _host(stats)[0])))
+        assert got == exp, f"stats step {t}"
+        _assert_same(model, S, f"after step {t}")
+
+
+@pytest.mark.parametrize("W,H,cap_s,cap_w,n_s0,n_w0", [
+    (1, 1, 40, 20, 12, 6), (2, 1, 30, 30, 14, 14), (3, 3, 60, 40, 30, 25), (17, 9, 5000, 3000, 900, 400),
+])
+def test_multi_prey_crowded_cells(abm, orc, W, H, cap_s, cap_w, n_s0, n_w0):
+    """Tens of wolves and sheep on one cell: every rank of the per-cell
+    matching is exercised, with more sheep than wolves and the reverse."""
+    for seed in range(8):
+        kw = dict(W=W, H=H, R=3, T_s=2 ** 30, T_w=2 ** 30, seed=seed, cap_s=cap_s, cap_w=cap_w,
+                  n_s0=n_s0, n_w0=n_w0, multi_prey=1)
+        P, S, model = _pair(abm, orc, **kw)
+        stats = torch.zeros((1, 8), dtype=torch.int64, device="cuda")
+        for t in range(12):
+            exp = orc.predation_step(P, S)
+            model.run(1, stats)
+            assert dict(zip(abm.STAT_NAMES, (int(v) for v in _host(stats)[0]))) == exp
+            _assert_same(model, S, f"seed {seed} step {t}")
+
+
+def test_multi_prey_large_workload(abm, orc):
+    """2048x2048 with multi_prey: two full comparisons, then bookkeeping."""
+    kw = dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000, n_w0=400_000,
+              seed=2, multi_prey=1)
+    P, S, model = _pair(abm, orc, **kw)
+    for t in range(2):
+        orc.predation_step(P, S)
+        model.run(1)
+        _assert_same(model, S, f"after step {t}")
+    n = 100
+    stats = torch.zeros((n, 8), dtype=torch.int64, device="cuda")
+    model.run(n, stats)
+    st = _host(stats)
+    for t in range(n - 1):
+        live_s, live_w, ge, se, bs, bw, ss, sw = (int(v) for v in st[t])
+        assert st[t + 1][0] == live_s - se - ss + bs, t
+        assert st[t + 1][1] == live_w - sw + bw, t
+        assert se <= min(live_s, live_w)
+    assert abm.workspace_error(model.ws) == 0
+
+
+def test_multi_prey_rejected_by_the_batched_form(abm):
+    with pytest.raises(ValueError):
+        abm.BatchedPredation([abm.predation_params(multi_prey=1)], 5)
