@@ -69,6 +69,26 @@ class PredStats(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class TrafficParams(C.Structure):
+    """Traffic CA parameters (Sec. 5.2; the paper gives no values)."""
+    _fields_ = [("length", C.c_int32), ("T_green", C.c_uint32), ("T_spawn", C.c_uint32),
+                ("seed", C.c_uint32)]
+
+
+class _TrafficState(C.Structure):
+    _fields_ = [("lane", C.POINTER(C.c_int32)), ("pos", C.POINTER(C.c_int32)),
+                ("alive", C.POINTER(C.c_int32)), ("step", C.c_uint32)]
+
+
+class TrafficStats(C.Structure):
+    _fields_ = [("cars", C.c_int64), ("exited", C.c_int64), ("moved", C.c_int64),
+                ("blocked", C.c_int64), ("lost", C.c_int64), ("waiting_red", C.c_int64),
+                ("spawned", C.c_int64), ("lane_changes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _P8 = C.POINTER(C.c_uint8)
 _P32 = C.POINTER(C.c_int32)
 _PU32 = C.POINTER(C.c_uint32)
@@ -104,6 +124,11 @@ def _declare(L):
     L.orc_predation_step.argtypes = [C.POINTER(PredParams), C.POINTER(_PredState),
                                      C.POINTER(PredStats)]
     L.orc_predation_step.restype = None
+    L.orc_traffic_init.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState)]
+    L.orc_traffic_init.restype = None
+    L.orc_traffic_step.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState),
+                                   C.POINTER(TrafficStats)]
+    L.orc_traffic_step.restype = None
 
 
 def _ptr(a: np.ndarray, ct):
@@ -320,3 +345,48 @@ def pred_die(P, S):
 
 def pred_regrow(P, S):
     _phase("orc_pred_regrow", P, S, 0)
+
+
+# ---------------------------------------------------------------- traffic
+TRAFFIC_STATS = tuple(k for k, _ in TrafficStats._fields_)
+
+
+def traffic_params(length=100, T_green=2 ** 31, T_spawn=2 ** 31, seed=0) -> TrafficParams:
+    return TrafficParams(length, T_green, T_spawn, seed)
+
+
+@dataclass
+class TrafficState:
+    """Host copy of one road: car slots (lane, pos, alive) and the step counter."""
+    lane: np.ndarray
+    pos: np.ndarray
+    alive: np.ndarray
+    step: int = 0
+
+    def copy(self) -> "TrafficState":
+        return TrafficState(self.lane.copy(), self.pos.copy(), self.alive.copy(), self.step)
+
+    def _c(self):
+        return _TrafficState(_ptr(self.lane, C.c_int32), _ptr(self.pos, C.c_int32),
+                             _ptr(self.alive, C.c_int32), self.step)
+
+
+def traffic_init(P: TrafficParams) -> TrafficState:
+    n = 3 * P.length
+    S = TrafficState(*(np.zeros(n, dtype=np.int32) for _ in range(3)))
+    cs = S._c()
+    lib().orc_traffic_init(C.byref(P), C.byref(cs))
+    S.step = int(cs.step)
+    return S
+
+
+def traffic_step(P: TrafficParams, S: TrafficState) -> dict:
+    cs = S._c()
+    st = TrafficStats()
+    lib().orc_traffic_step(C.byref(P), C.byref(cs), C.byref(st))
+    S.step = int(cs.step)
+    return st.as_dict()
+
+
+def traffic_run(P: TrafficParams, S: TrafficState, n_steps: int) -> list:
+    return [traffic_step(P, S) for _ in range(n_steps)]

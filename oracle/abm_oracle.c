@@ -566,3 +566,147 @@ ORC_API void orc_predation_run(const orc_pred_params* P, orc_pred_state* S, int3
     for (int32_t k = 0; k < n_steps; ++k)
         orc_predation_step(P, S, stats ? &stats[k] : NULL);
 }
+
+/* ------------------------------------------------------------------------- */
+/* 5. Traffic cellular automaton (Sec. 5.2, Fig. 4).                           */
+/*                                                                           */
+/* A road of 3 lanes x L cells; cell (lane, x), x = 0 the entry column and     */
+/* x = L-1 the exit column.  Cars are agents in 3L slots with attributes lane,  */
+/* pos and alive.  The paper fixes the ingredients (entry cells, exit cells     */
+/* under signals, random lane changes, one car per cell, conflicts resolved by  */
+/* cells acting as agents with a priority mask over their incoming directions,  */
+/* spawning into free entry cells) but no numbers; the rules below are the      */
+/* reading used here.  Step t:                                                 */
+/*   1. lights: exit lane l is green iff draw(t, l, LIGHT) < T_green;          */
+/*   2. every car decides on the occupancy at the start of the step: a car in  */
+/*      the exit column leaves if its light is green and waits otherwise; any */
+/*      other car picks left / straight / right uniformly (Lemire reduction of */
+/*      draw(t, slot, LANE) onto 3; a lane off the road means straight) and    */
+/*      claims the cell one column ahead in that lane, unless it is occupied  */
+/*      (then it waits);                                                      */
+/*   3. each claimed cell admits one claimant: the one arriving straight, else */
+/*      the one from the lane below, else the one from the lane above (the     */
+/*      cell's priority mask; resolve_conflicts with those priorities);       */
+/*      winners move, the others wait;                                        */
+/*   4. leaving cars are removed (remove_agents);                             */
+/*   5. every entry cell l that is free now spawns a car if draw(t, l, SPAWN) */
+/*      < T_spawn; the spawned cars, in lane order, go to the lowest free     */
+/*      slots (add_agents).                                                    */
+/* ------------------------------------------------------------------------- */
+
+enum { P_T_LIGHT = 0x30, P_T_LANE = 0x31, P_T_SPAWN = 0x32 };
+
+typedef struct {
+    int32_t length;           /* cells per lane, >= 2 */
+    uint32_t T_green, T_spawn;
+    uint32_t seed;
+} orc_traffic_params;
+
+typedef struct {
+    int32_t *lane, *pos, *alive;   /* [3 * length] car slots */
+    uint32_t step;
+} orc_traffic_state;
+
+typedef struct {
+    int64_t cars;          /* at the start of the step */
+    int64_t exited, moved, blocked, lost, waiting_red, spawned;
+    int64_t lane_changes;
+} orc_traffic_stats;
+
+ORC_API void orc_traffic_init(const orc_traffic_params* P, orc_traffic_state* S)
+{
+    for (int64_t i = 0; i < 3 * (int64_t)P->length; ++i) {
+        S->lane[i] = 0; S->pos[i] = 0; S->alive[i] = 0;
+    }
+    S->step = 0;
+}
+
+ORC_API void orc_traffic_step(const orc_traffic_params* P, orc_traffic_state* S,
+                              orc_traffic_stats* st)
+{
+    const int64_t L = P->length, n = 3 * L;
+    const uint32_t t = S->step;
+    orc_traffic_stats loc;
+    memset(&loc, 0, sizeof loc);
+    int32_t* occ = (int32_t*)malloc((size_t)n * sizeof(int32_t));      /* cell -> slot or -1 */
+    int32_t* target = (int32_t*)malloc((size_t)n * sizeof(int32_t));   /* slot -> claimed cell */
+    uint32_t* prio = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+    uint8_t* active = (uint8_t*)malloc((size_t)n);
+    uint8_t* leave = (uint8_t*)malloc((size_t)n);
+    uint64_t* best = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+    int32_t* winner = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    uint8_t* won = (uint8_t*)malloc((size_t)n);
+    int green[3];
+
+    for (int64_t c = 0; c < n; ++c) occ[c] = -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (S->alive[i]) { occ[(int64_t)S->lane[i] * L + S->pos[i]] = (int32_t)i; loc.cars++; }
+    for (int l = 0; l < 3; ++l) green[l] = orc_rng(P->seed, t, (uint32_t)l, P_T_LIGHT) < P->T_green;
+
+    /* 2. decisions on the start-of-step occupancy */
+    for (int64_t i = 0; i < n; ++i) {
+        active[i] = 0; leave[i] = 0; target[i] = -1; prio[i] = 0;
+        if (!S->alive[i]) continue;
+        const int32_t l = S->lane[i], x = S->pos[i];
+        if (x == L - 1) {
+            if (green[l]) leave[i] = 1; else loc.waiting_red++;
+            continue;
+        }
+        int32_t dl = (int32_t)orc_uniform(orc_rng(P->seed, t, (uint32_t)i, P_T_LANE), 3u) - 1;
+        int32_t nl = l + dl;
+        if (nl < 0 || nl > 2) nl = l;
+        const int64_t c = (int64_t)nl * L + (x + 1);
+        if (occ[c] >= 0) { loc.blocked++; continue; }
+        target[i] = (int32_t)c;
+        active[i] = 1;
+        /* the target cell's priority over its three incoming directions */
+        prio[i] = nl == l ? 0u : (l < nl ? 1u : 2u);
+    }
+    /* 3. one claimant per cell */
+    orc_resolve_conflicts(n, target, prio, active, n, best, winner, won);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!active[i]) continue;
+        if (won[i]) {
+            const int32_t nl = target[i] / (int32_t)L;
+            if (nl != S->lane[i]) loc.lane_changes++;
+            S->lane[i] = nl;
+            S->pos[i] = target[i] % (int32_t)L;
+            loc.moved++;
+        } else {
+            loc.lost++;
+        }
+    }
+    /* 4. exits */
+    {
+        int64_t removed = 0;
+        orc_remove_agents(n, S->alive, leave, &removed);
+        loc.exited = removed;
+    }
+    /* 5. spawning into free entry cells */
+    {
+        int32_t free_entry[3] = {1, 1, 1};
+        for (int64_t i = 0; i < n; ++i)
+            if (S->alive[i] && S->pos[i] == 0) free_entry[S->lane[i]] = 0;
+        int32_t rec_lane[3], rec_pos[3];
+        int64_t q = 0;
+        for (int l = 0; l < 3; ++l)
+            if (free_entry[l] && orc_rng(P->seed, t, (uint32_t)l, P_T_SPAWN) < P->T_spawn) {
+                rec_lane[q] = l; rec_pos[q] = 0; ++q;
+            }
+        int32_t* attr[2] = {S->lane, S->pos};
+        const int32_t* rec[2] = {rec_lane, rec_pos};
+        int64_t added = 0, dropped = 0;
+        orc_add_agents(n, 2, attr, S->alive, q, rec, &added, &dropped);
+        loc.spawned = added;
+    }
+    free(occ); free(target); free(prio); free(active); free(leave);
+    free(best); free(winner); free(won);
+    S->step += 1;
+    if (st) *st = loc;
+}
+
+ORC_API void orc_traffic_run(const orc_traffic_params* P, orc_traffic_state* S, int32_t n_steps,
+                             orc_traffic_stats* stats)
+{
+    for (int32_t k = 0; k < n_steps; ++k) orc_traffic_step(P, S, stats ? &stats[k] : NULL);
+}
