@@ -202,6 +202,29 @@ def predation_leg(abm, torch, kw, steps, label):
             "workspace_error": err}
 
 
+def traffic_leg(abm, torch, n_roads=500, length=100, steps=1000):
+    """Traffic CA (Sec. 5.2): n_roads roads of 3 x length cells, `steps` steps in
+    one call (one workgroup per road, the road held in LDS); car updates per
+    second = cars at the start of each step, summed over roads and steps."""
+    roads = abm.TrafficRoads(abm.traffic_params(length, seed=1), n_roads)
+    roads.init()
+    roads.run(10)                                  # warm-up: the roads fill up
+    stats = torch.zeros((steps, n_roads, 8), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    roads.run(steps, stats)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cars = int(stats[:, :, 0].sum().item())
+    del roads, stats
+    return {"workload": f"{n_roads} roads of 3 x {length} cells, {steps} steps in one call, "
+                        "lights and spawns with probability 1/2, seeds 1..", "steps": steps,
+            "ms": ms, "car_updates": cars, "car_updates_per_s": cars / (ms / 1e3)}
+
+
 def served_leg(seconds, rate=200.0, team_size=1, team_min_size=1 << 18):
     """Served form: Poisson arrivals (rate/s for `seconds`), grid side log-uniform
     in [32, 1024], steps log-uniform in [100, 5000], admitted by HBM footprint
@@ -384,6 +407,7 @@ def main():
                              n_w0=400_000, seed=0, multi_prey=1), 999,
             "2048x2048 torus as above with prey matched by rank within each cell (the r-th "
             "wolf of a cell eats its r-th sheep), steps 1-999 after a warm-up step")
+        out["traffic"] = traffic_leg(abm, torch)
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()
     if args.served_seconds > 0:

@@ -338,6 +338,52 @@ ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, 
  * the grass array of the one-model state.  countdown: device int32[sum of W*H]. */
 ABM_API int abm_predation_batched_grass(const abm_batch* b, int32_t* countdown, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Traffic cellular automaton (Sec. 5.2, Fig. 4), many roads at once (the
+ * paper vectorises it over roads with different car counts, Table 3).  A road
+ * is 3 lanes x length cells; cell (lane, x), x = 0 the entry column, x =
+ * length - 1 the exit column.  Cars occupy 3 * length slots (lane, pos,
+ * alive).  Step t of road r, with draws keyed on (seed + r, t, agent,
+ * purpose):
+ *   lights  exit lane l is green iff its draw < T_green;
+ *   decide  on the occupancy at the start of the step, a car in the exit
+ *           column leaves under green and waits under red; any other car
+ *           picks left / straight / right uniformly (off the road means
+ *           straight) and claims the cell one column ahead in that lane
+ *           unless it is occupied (then it waits);
+ *   resolve each claimed cell admits one car, by its priority mask over the
+ *           arrival directions: straight, then from the lane below, then
+ *           from the lane above; winners move, the others wait;
+ *   leave   leaving cars get alive = 0 (their other fields are kept);
+ *   spawn   every entry cell free after the moves whose draw < T_spawn gets a
+ *           car; the spawned cars, in lane order, take the lowest free slots.
+ * ------------------------------------------------------------------------- */
+typedef struct abm_traffic_params {
+    int32_t length;        /* cells per lane, in [2, 1024] */
+    uint32_t T_green;      /* a light is green when its draw < T_green */
+    uint32_t T_spawn;      /* a free entry cell spawns a car when its draw < T_spawn */
+    uint32_t seed;         /* road r draws with seed + r (mod 2^32) */
+} abm_traffic_params;
+
+typedef struct abm_traffic_state {
+    int32_t n_roads;       /* in [1, 2^20] */
+    int32_t* lane;         /* device int32[n_roads * 3 * length]; road r at [r*3L, (r+1)*3L) */
+    int32_t* pos;
+    int32_t* alive;
+    int64_t* stats;        /* device int64[n_steps][n_roads][8] or NULL: per step and road
+                              cars (at step start), exited, moved, blocked, lost (a conflict),
+                              waiting_red, spawned, lane_changes */
+    uint32_t step;         /* (host) index of the next step; advanced by the call */
+} abm_traffic_state;
+
+/* Empty roads (every slot alive = 0, lane = pos = 0); sets s->step = 0. */
+ABM_API int abm_traffic_init(const abm_traffic_params* p, abm_traffic_state* s, void* stream);
+
+/* Run n_steps steps of every road from s->step, then advance s->step.  One
+ * workgroup per road keeps the road in LDS for the whole call. */
+ABM_API int abm_traffic_step(const abm_traffic_params* p, abm_traffic_state* s, int32_t n_steps,
+                             void* stream);
+
 /* Message describing the last non-OK status returned on this thread. */
 ABM_API const char* abm_last_error(void);
 

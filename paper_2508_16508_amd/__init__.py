@@ -29,7 +29,7 @@ EXPORTED = (
     "abm_predation_step", "abm_last_error", "abm_version", "abm_batched_workspace_bytes",
     "abm_predation_batched_init", "abm_predation_run_batched", "abm_predation_batched_grass",
     "abm_select_update_batched", "abm_add_agents_batched", "abm_remove_agents_batched",
-    "abm_resolve_conflicts_batched",
+    "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
 )
 
 
@@ -55,6 +55,16 @@ class PredationParams(C.Structure):
                 ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
                 ("cap_s", C.c_int64), ("cap_w", C.c_int64),
                 ("n_s0", C.c_int64), ("n_w0", C.c_int64), ("multi_prey", C.c_int32)]
+
+
+class TrafficParams(C.Structure):
+    _fields_ = [("length", C.c_int32), ("T_green", C.c_uint32), ("T_spawn", C.c_uint32),
+                ("seed", C.c_uint32)]
+
+
+class TrafficStatePtrs(C.Structure):
+    _fields_ = [("n_roads", C.c_int32), ("lane", C.c_void_p), ("pos", C.c_void_p),
+                ("alive", C.c_void_p), ("stats", C.c_void_p), ("step", C.c_uint32)]
 
 
 class SpeciesPtrs(C.Structure):
@@ -550,3 +560,48 @@ class BatchedPredation:
         sheep = {k: v[dm.sheep_off: dm.sheep_off + p.cap_s] for k, v in self.sheep.items()}
         wolves = {k: v[dm.wolf_off: dm.wolf_off + p.cap_w] for k, v in self.wolves.items()}
         return grass, sheep, wolves
+
+
+# ---------------------------------------------------------------- traffic
+TRAFFIC_STAT_NAMES = ("cars", "exited", "moved", "blocked", "lost", "waiting_red", "spawned",
+                      "lane_changes")
+
+
+def traffic_params(length=100, T_green=2 ** 31, T_spawn=2 ** 31, seed=0) -> TrafficParams:
+    """Traffic CA of Sec. 5.2: 3 lanes x `length` cells; lights and spawns
+    succeed when a draw is below the threshold (2^31: probability 1/2)."""
+    return TrafficParams(length, T_green, T_spawn, seed)
+
+
+class TrafficRoads:
+    """n_roads roads of one length, device-resident: car slots (lane, pos,
+    alive) as int32 [n_roads, 3 * length]; road r draws with seed + r."""
+
+    def __init__(self, params: TrafficParams, n_roads: int, device="cuda"):
+        self.params = params
+        self.n_roads = n_roads
+        n = 3 * params.length
+        z = lambda: torch.zeros((n_roads, n), dtype=torch.int32, device=device)
+        self.lane, self.pos, self.alive = z(), z(), z()
+        self.step = 0
+
+    def _ptrs(self, stats=None) -> TrafficStatePtrs:
+        return TrafficStatePtrs(self.n_roads, self.lane.data_ptr(), self.pos.data_ptr(),
+                                self.alive.data_ptr(),
+                                stats.data_ptr() if stats is not None else None, self.step)
+
+    def init(self, stream=None):
+        st = self._ptrs()
+        _check(lib().abm_traffic_init(C.byref(self.params), C.byref(st), _stream(stream)))
+        self.step = int(st.step)
+
+    def run(self, n_steps: int, stats: torch.Tensor | None = None, stream=None):
+        """Advance every road n_steps; stats (int64 [n_steps, n_roads, 8])
+        receives per-step counts (TRAFFIC_STAT_NAMES)."""
+        if stats is not None:
+            _require(stats, torch.int64, "stats")
+            assert stats.numel() >= 8 * n_steps * self.n_roads
+        st = self._ptrs(stats)
+        _check(lib().abm_traffic_step(C.byref(self.params), C.byref(st), n_steps,
+                                      _stream(stream)))
+        self.step = int(st.step)

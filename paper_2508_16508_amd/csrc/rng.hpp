@@ -1,4 +1,5 @@
-// rng.hpp -- device-side counter-based random draws for the predation model.
+// rng.hpp -- device-side counter-based random draws for the predation and
+// traffic models.
 //
 // A draw is keyed on (seed, step, agent, purpose) and carries no state, so a
 // model resumes bit-exactly from its state and step counter.  The mixer is the
@@ -44,7 +45,8 @@ enum Purpose : uint32_t {
     kSheepX = 0x10, kSheepY = 0x11, kSheepE = 0x12, kSheepMove = 0x13,
     kSheepGrassKey = 0x14, kSheepPreyKey = 0x15, kSheepBreed = 0x16,
     kWolfX = 0x20, kWolfY = 0x21, kWolfE = 0x22, kWolfMove = 0x23,
-    kWolfEatKey = 0x24, kWolfBreed = 0x26
+    kWolfEatKey = 0x24, kWolfBreed = 0x26,
+    kTrafficLight = 0x30, kTrafficLane = 0x31, kTrafficSpawn = 0x32
 };
 
 constexpr uint32_t kInitStep = 0xFFFFFFFFu;
