@@ -124,6 +124,10 @@ def _declare(L):
     L.orc_predation_step.argtypes = [C.POINTER(PredParams), C.POINTER(_PredState),
                                      C.POINTER(PredStats)]
     L.orc_predation_step.restype = None
+    L.orc_sort_agents.argtypes = [C.c_int64, C.c_int32, _PP32, _P32, _P32, C.c_int32, _P32]
+    L.orc_sort_agents.restype = None
+    L.orc_select_agents.argtypes = [_P8, C.c_int64, _P32]
+    L.orc_select_agents.restype = C.c_int64
     L.orc_traffic_init.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState)]
     L.orc_traffic_init.restype = None
     L.orc_traffic_step.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState),
@@ -345,6 +349,30 @@ def pred_die(P, S):
 
 def pred_regrow(P, S):
     _phase("orc_pred_regrow", P, S, 0)
+
+
+# ---------------------------------------------------------------- sort / select
+def sort_agents(attrs, key, descending=False, alive=None):
+    """Returns (sorted attrs [A, n], sorted alive or None, perm int32[n])."""
+    out = np.array(attrs, dtype=np.int32, order="C", copy=True)
+    key = np.ascontiguousarray(key, dtype=np.int32)
+    n = key.size
+    assert out.shape[1] == n
+    al = None if alive is None else np.array(alive, dtype=np.int32, copy=True)
+    perm = np.empty(max(1, n), dtype=np.int32)
+    lib().orc_sort_agents(n, out.shape[0], _ptr_array(out),
+                          _ptr(al, C.c_int32) if al is not None else None,
+                          _ptr(key, C.c_int32), int(bool(descending)), _ptr(perm, C.c_int32))
+    return out, al, perm[:n].copy()
+
+
+def select_agents(cond):
+    """Returns (order int32[n]: satisfying indices first, both groups in index
+    order; count)."""
+    cond = np.ascontiguousarray(cond, dtype=np.uint8)
+    order = np.empty(max(1, cond.size), dtype=np.int32)
+    p = lib().orc_select_agents(_ptr(cond, C.c_uint8), cond.size, _ptr(order, C.c_int32))
+    return order[:cond.size].copy(), int(p)
 
 
 # ---------------------------------------------------------------- traffic

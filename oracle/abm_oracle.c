@@ -710,3 +710,61 @@ ORC_API void orc_traffic_run(const orc_traffic_params* P, orc_traffic_state* S, 
 {
     for (int32_t k = 0; k < n_steps; ++k) orc_traffic_step(P, S, stats ? &stats[k] : NULL);
 }
+
+/* ------------------------------------------------------------------------- */
+/* 6. sort_agents and select_agents (Sec. 2 API list).                         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { int32_t key; int64_t idx; } key_idx;
+
+static int cmp_key_asc(const void* a, const void* b)
+{
+    const key_idx* x = (const key_idx*)a;
+    const key_idx* y = (const key_idx*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+static int cmp_key_desc(const void* a, const void* b)
+{
+    const key_idx* x = (const key_idx*)a;
+    const key_idx* y = (const key_idx*)b;
+    if (x->key != y->key) return x->key > y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+/* sort_agents: reorder every attribute of the collection by the runtime key
+ * (one int32 per agent), ascending or descending; agents with equal keys keep
+ * their index order (a stable sort).  perm[j] = the old index of the agent now
+ * at position j (may be NULL).  alive, if given, is reordered like the
+ * attributes. */
+ORC_API void orc_sort_agents(int64_t n, int32_t n_attrs, int32_t* const* attr, int32_t* alive,
+                             const int32_t* key, int32_t descending, int32_t* perm)
+{
+    key_idx* ki = (key_idx*)malloc((size_t)(n > 0 ? n : 1) * sizeof(key_idx));
+    int32_t* tmp = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) { ki[i].key = key[i]; ki[i].idx = i; }
+    qsort(ki, (size_t)n, sizeof(key_idx), descending ? cmp_key_desc : cmp_key_asc);
+    for (int32_t a = -1; a < n_attrs; ++a) {
+        int32_t* col = a < 0 ? alive : attr[a];
+        if (!col) continue;
+        for (int64_t j = 0; j < n; ++j) tmp[j] = col[ki[j].idx];
+        memcpy(col, tmp, (size_t)n * sizeof(int32_t));
+    }
+    if (perm)
+        for (int64_t j = 0; j < n; ++j) perm[j] = (int32_t)ki[j].idx;
+    free(ki); free(tmp);
+}
+
+/* select_agents: the indices of the agents that satisfy the condition, in
+ * index order, then the others, in index order; returns how many satisfy it. */
+ORC_API int64_t orc_select_agents(const uint8_t* cond, int64_t n, int32_t* order)
+{
+    int64_t p = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (cond[i]) order[p++] = (int32_t)i;
+    int64_t q = p;
+    for (int64_t i = 0; i < n; ++i)
+        if (!cond[i]) order[q++] = (int32_t)i;
+    return p;
+}
