@@ -202,6 +202,45 @@ def predation_leg(abm, torch, kw, steps, label):
             "workspace_error": err}
 
 
+def sort_select_leg(abm, torch, W, n=1 << 24, reps=5):
+    """sort_agents on the microbenchmark's collection (2^24 agents x 8 int32
+    attributes + alive, full-range random int32 keys; radix sort plus the
+    gather of 9 columns) and select_agents (stable partition) at p = 0.05."""
+    import numpy as np
+    dev = torch.device("cuda")
+    g = np.random.default_rng(7)
+    key = torch.from_numpy(g.integers(-2 ** 31, 2 ** 31, size=n, dtype=np.int64)
+                           .astype(np.int32)).to(dev)
+    attrs = torch.from_numpy(W.int32_rows(8, 8, n)).to(dev)
+    alive = torch.ones(n, dtype=torch.int32, device=dev)
+    cond = torch.from_numpy(W.bernoulli_mask(3, 0.05, n)).to(dev)
+    ws = abm.sort_workspace(n, dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = {}
+    for name, fn in (("sort_agents", lambda: abm.sort_agents(attrs, key, alive=alive, perm=perm,
+                                                              ws=ws)),
+                     ("select_agents", lambda: abm.select_agents(cond, order=order, ws=ws,
+                                                                  count=count))):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "agents_per_s": n / (ms / 1e3)}
+    out["workload"] = ("2^24 agents x 8 int32 attributes + alive, full-range random int32 keys "
+                       "(sort), Bernoulli(0.05) condition (select); mean of 5 calls")
+    del key, attrs, alive, cond, ws, perm, order
+    torch.cuda.empty_cache()
+    return out
+
+
 def traffic_leg(abm, torch, n_roads=500, length=100, steps=1000):
     """Traffic CA (Sec. 5.2): n_roads roads of 3 x length cells, `steps` steps in
     one call (one workgroup per road, the road held in LDS); car updates per
@@ -408,6 +447,7 @@ def main():
             "2048x2048 torus as above with prey matched by rank within each cell (the r-th "
             "wolf of a cell eats its r-th sheep), steps 1-999 after a warm-up step")
         out["traffic"] = traffic_leg(abm, torch)
+        out["sort_select"] = sort_select_leg(abm, torch, W)
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()
     if args.served_seconds > 0:

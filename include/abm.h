@@ -339,6 +339,29 @@ ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, 
 ABM_API int abm_predation_batched_grass(const abm_batch* b, int32_t* countdown, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * sort_agents and select_agents (Sec. 2 API list).
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for abm_sort_agents / abm_select_agents over n agents
+ * (about 20 n bytes); 0 for n outside [0, 2^31). */
+ABM_API size_t abm_sort_workspace_bytes(int64_t n);
+
+/* Reorder the collection by a runtime key (Sec. 2 sort_agents): afterwards
+ * position j holds the agent that had the j-th smallest key (descending != 0:
+ * the j-th largest); agents with equal keys keep their index order.  Every
+ * attribute column and, if non-NULL, alive are permuted in place.  key: device
+ * int32[capacity].  perm (device int32[capacity], may be NULL) receives the old
+ * index of the agent now at each position. */
+ABM_API int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t descending,
+                            int32_t* perm, void* ws, size_t ws_bytes, void* stream);
+
+/* Sec. 2 select_agents: order (device int32[n]) receives the indices i with
+ * cond[i] != 0 in increasing order, then the others in increasing order;
+ * *d_count (device int64) the number of the former. */
+ABM_API int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order, int64_t* d_count,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Traffic cellular automaton (Sec. 5.2, Fig. 4), many roads at once (the
  * paper vectorises it over roads with different car counts, Table 3).  A road
  * is 3 lanes x length cells; cell (lane, x), x = 0 the entry column, x =

@@ -30,6 +30,7 @@ EXPORTED = (
     "abm_predation_batched_init", "abm_predation_run_batched", "abm_predation_batched_grass",
     "abm_select_update_batched", "abm_add_agents_batched", "abm_remove_agents_batched",
     "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
+    "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents",
 )
 
 
@@ -250,6 +251,47 @@ def select_indices(mask, out_idx=None, ws=None, count=None, stream=None):
     _check(lib().abm_select_indices(_p(mask), n, _p(out_idx), _p(count), _p(ws), ws.numel(),
                                     _stream(stream)))
     return out_idx, count
+
+
+def sort_workspace(n: int, device="cuda") -> torch.Tensor:
+    """A 256-byte-aligned workspace for sort_agents / select_agents over n agents."""
+    nbytes = int(lib().abm_sort_workspace_bytes(C.c_int64(n)))
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off: off + nbytes]
+
+
+def sort_agents(attrs, key, descending=False, alive=None, perm=None, ws=None, stream=None):
+    """Reorder the collection in place by a runtime int32 key (Sec. 2
+    sort_agents; stable, ascending or descending).  Returns perm int32[n]: the
+    old index of the agent now at each position."""
+    _require(key, torch.int32, "key")
+    dst = make_soa(attrs, alive)
+    dst.capacity = key.numel()
+    dev = key.device
+    if perm is None:
+        perm = torch.empty(max(1, key.numel()), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = sort_workspace(key.numel(), dev)
+    _check(lib().abm_sort_agents(C.byref(dst), _p(key), int(bool(descending)), _p(perm), _p(ws),
+                                 ws.numel(), _stream(stream)))
+    return perm
+
+
+def select_agents(cond, order=None, ws=None, count=None, stream=None):
+    """Sec. 2 select_agents: (order int32[n] -- the indices satisfying cond in
+    increasing order, then the others -- and count int64[1])."""
+    _require(cond, torch.uint8, "cond")
+    n = cond.numel()
+    dev = cond.device
+    if order is None:
+        order = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = sort_workspace(n, dev)
+    (count,) = _counts(dev, count)
+    _check(lib().abm_select_agents(_p(cond), n, _p(order), _p(count), _p(ws), ws.numel(),
+                                   _stream(stream)))
+    return order, count
 
 
 def add_agents(attrs, alive, recs, ws=None, added=None, dropped=None, stream=None):

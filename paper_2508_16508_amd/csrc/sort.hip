@@ -1,0 +1,382 @@
+// sort.hip -- abm_sort_agents and abm_select_agents (the Sec. 2 API's
+// sort_agents and select_agents).
+//
+// sort_agents is a least-significant-digit radix sort of (key, slot) pairs
+// with 8-bit digits, four passes over 32-bit keys, followed by a gather of
+// every attribute column through the resulting permutation.  Each pass is
+//   histogram  per 4096-key tile, 256 bins in LDS, stored digit-major;
+//   scan       one workgroup per digit scans that digit's tile counts (the
+//              tile's offset within the digit's bucket), and one workgroup
+//              turns the 256 digit totals into bucket bases;
+//   scatter    each tile ranks its keys stably: a wave takes its 16 items in
+//              order, finds the lanes holding the same digit with eight
+//              ballots (one per digit bit), and ranks a lane after the
+//              same-digit lanes below it and the same-digit keys of the
+//              wave's earlier items (running per-wave counters in LDS); wave
+//              offsets per digit follow from the wave totals.  A key's
+//              destination is base[d] + tile offset[d] + wave offset[d] + rank.
+// Keys in a tile are laid out wave-major, then item, then lane, so that the
+// lane order inside an item is the index order and every pass is stable.  A
+// signed key becomes an unsigned one with the sign bit flipped (ascending)
+// and then all bits flipped (descending), so the descending sort keeps equal
+// keys in index order too.
+//
+// select_agents is one such pass on a 1-bit digit (0 for agents that satisfy
+// the condition): a stable partition whose permutation is the index list.
+#include <hip/hip_runtime.h>
+
+#include "abm.h"
+#include "common.hpp"
+#include "scan.hpp"
+
+namespace abm {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = kWaves * 64;
+constexpr int kItems = 16;
+constexpr int64_t kTile = int64_t(kBlock) * kItems;   // 4096 keys
+constexpr int kBins = 256;
+
+enum KeySource : int {
+    kFromKeys = 0,      // first pass: int32 keys, slot = index
+    kFromBuffer = 1,    // later passes: (ukey, slot) ping-pong buffers
+    kFromCond = 2       // select_agents: digit = (cond == 0)
+};
+
+struct PassArgs {
+    const int32_t* key;        // kFromKeys
+    const uint8_t* cond;       // kFromCond
+    const uint32_t* in_key;    // kFromBuffer
+    const int32_t* in_val;
+    uint32_t* out_key;
+    int32_t* out_val;
+    uint32_t* counts;          // [kBins][n_tiles]: tile counts, then tile offsets
+    uint32_t* totals;          // [kBins]
+    uint32_t* base;            // [kBins]
+    int64_t n;
+    uint32_t n_tiles;
+    uint32_t shift;
+    uint32_t flip;             // xor applied to the sign-flipped key (0 or ~0)
+};
+
+// Slot of item k of lane l of wave w in tile t.
+__device__ __forceinline__ int64_t slot_of(uint32_t t, int w, int k, int l) {
+    return int64_t(t) * kTile + int64_t(w) * (kItems * 64) + k * 64 + l;
+}
+
+template <int SRC>
+__device__ __forceinline__ void load_item(const PassArgs& a, int64_t i, uint32_t& ukey,
+                                          int32_t& val, uint32_t& digit) {
+    if (SRC == kFromKeys) {
+        ukey = (uint32_t(a.key[i]) ^ 0x80000000u) ^ a.flip;
+        val = int32_t(i);
+        digit = (ukey >> a.shift) & 0xFFu;
+    } else if (SRC == kFromBuffer) {
+        ukey = a.in_key[i];
+        val = a.in_val[i];
+        digit = (ukey >> a.shift) & 0xFFu;
+    } else {
+        ukey = 0;
+        val = int32_t(i);
+        digit = a.cond[i] ? 0u : 1u;
+    }
+}
+
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
+    __shared__ uint32_t hist[kBins];
+    const uint32_t t = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < kBins; d += kBlock) hist[d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = slot_of(t, w, k, lane);
+        if (i >= a.n) continue;
+        uint32_t ukey, digit;
+        int32_t val;
+        load_item<SRC>(a, i, ukey, val, digit);
+        atomicAdd(&hist[digit], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kBins; d += kBlock) a.counts[int64_t(d) * a.n_tiles + t] = hist[d];
+}
+
+// One workgroup per digit: exclusive scan of the digit's tile counts in place;
+// the digit's total to totals[d].
+__global__ __launch_bounds__(kBlock) void k_digit_scan(PassArgs a) {
+    __shared__ uint32_t lds[kWaves + 1];
+    uint32_t* row = a.counts + int64_t(blockIdx.x) * a.n_tiles;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < a.n_tiles; c0 += kBlock) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t v = i < a.n_tiles ? row[i] : 0u;
+        // inclusive scan within the wave
+        uint32_t x = v;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) lds[w] = x;
+        __syncthreads();
+        uint32_t before = carry, all = carry;
+        for (int q = 0; q < kWaves; ++q) {
+            before += q < w ? lds[q] : 0u;
+            all += lds[q];
+        }
+        if (i < a.n_tiles) row[i] = before + x - v;
+        carry = all;
+    }
+    if (threadIdx.x == 0) a.totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kBins) void k_digit_base(PassArgs a) {
+    __shared__ uint32_t lds[kBins / 64 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t v = a.totals[threadIdx.x];
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int q = 0; q < w; ++q) before += lds[q];
+    a.base[threadIdx.x] = before + x - v;
+}
+
+// Lanes of the wave whose digit equals this lane's (among the active lanes).
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t digit, bool active, int bits) {
+    uint64_t m = __ballot(active);
+    for (int b = 0; b < bits; ++b) {
+        const uint64_t set = __ballot(active && ((digit >> b) & 1u));
+        m &= ((digit >> b) & 1u) ? set : ~set;
+    }
+    return m;
+}
+
+template <int SRC>
+__global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
+    __shared__ uint32_t wcount[kWaves][kBins];   // running, then exclusive across waves
+    const uint32_t t = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bits = SRC == kFromCond ? 1 : 8;
+    for (int d = threadIdx.x; d < kWaves * kBins; d += kBlock) (&wcount[0][0])[d] = 0;
+    __syncthreads();
+    uint32_t key[kItems], dig[kItems], rank[kItems];
+    int32_t val[kItems];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = slot_of(t, w, k, lane);
+        const bool active = i < a.n;
+        key[k] = 0;
+        val[k] = 0;
+        dig[k] = 0;
+        if (active) load_item<SRC>(a, i, key[k], val[k], dig[k]);
+        const uint64_t peers = same_digit_lanes(dig[k], active, bits);
+        // the lowest peer reads and advances the wave's counter for this digit
+        const uint32_t before = active ? wcount[w][dig[k]] : 0u;
+        rank[k] = before + uint32_t(__popcll(peers & below));
+        // every peer has read the counter before the leader advances it
+        __builtin_amdgcn_wave_barrier();
+        if (active && (peers & below) == 0)
+            wcount[w][dig[k]] = before + uint32_t(__popcll(peers));
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // exclusive offsets of the waves within each digit of the tile
+    for (int d = threadIdx.x; d < kBins; d += kBlock) {
+        uint32_t run = 0;
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t c = wcount[q][d];
+            wcount[q][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = slot_of(t, w, k, lane);
+        if (i >= a.n) continue;
+        const uint32_t d = dig[k];
+        const int64_t dst = int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] +
+                            wcount[w][d] + rank[k];
+        if (SRC != kFromCond) a.out_key[dst] = key[k];
+        a.out_val[dst] = val[k];
+    }
+}
+
+// out[j] = col[perm[j]]
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ perm,
+                                                   int32_t* __restrict__ out, int64_t n) {
+    for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < n;
+         j += int64_t(gridDim.x) * kBlock)
+        out[j] = col[perm[j]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src,
+                                                 int32_t* __restrict__ dst, int64_t n) {
+    for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < n;
+         j += int64_t(gridDim.x) * kBlock)
+        dst[j] = src[j];
+}
+
+__global__ void k_count_out(const uint32_t* totals, int64_t* d_count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_count = totals ? int64_t(totals[0]) : 0;
+}
+
+struct SortWs {
+    uint32_t *key_a, *key_b;
+    int32_t *val_a, *val_b, *stage;
+    uint32_t *counts, *totals, *base;
+};
+
+uint32_t tiles_of(int64_t n) { return uint32_t((n + kTile - 1) / kTile); }
+
+size_t sort_ws_bytes(int64_t n) {
+    const int64_t t = tiles_of(n > 0 ? n : 1);
+    const int64_t m = n > 0 ? n : 1;
+    return size_t(4 * (5 * m + int64_t(kBins) * t + 2 * kBins) + 9 * 256);
+}
+
+SortWs carve_sort(void* ws, int64_t n) {
+    const int64_t m = n > 0 ? n : 1;
+    char* p = static_cast<char*>(ws);
+    auto take = [&](int64_t bytes) {
+        char* q = p;
+        p += (bytes + 255) / 256 * 256;
+        return q;
+    };
+    SortWs s;
+    s.key_a = reinterpret_cast<uint32_t*>(take(4 * m));
+    s.key_b = reinterpret_cast<uint32_t*>(take(4 * m));
+    s.val_a = reinterpret_cast<int32_t*>(take(4 * m));
+    s.val_b = reinterpret_cast<int32_t*>(take(4 * m));
+    s.stage = reinterpret_cast<int32_t*>(take(4 * m));
+    s.counts = reinterpret_cast<uint32_t*>(take(4 * int64_t(kBins) * tiles_of(m)));
+    s.totals = reinterpret_cast<uint32_t*>(take(4 * kBins));
+    s.base = reinterpret_cast<uint32_t*>(take(4 * kBins));
+    return s;
+}
+
+template <int SRC>
+void launch_pass(const PassArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_hist<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_digit_scan, dim3(kBins), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_digit_base, dim3(1), dim3(kBins), 0, st, a);
+    hipLaunchKernelGGL(k_scatter<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
+}
+
+dim3 stream_grid(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return dim3(uint32_t(b < 8192 ? (b > 0 ? b : 1) : 8192));
+}
+
+int check_sort_ws(void* ws, size_t ws_bytes, int64_t n) {
+    const size_t need = sort_ws_bytes(n);
+    if (!ws || ws_bytes < need) {
+        set_error("workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return ABM_E_WORKSPACE;
+    }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(ABM_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return ABM_OK;
+}
+
+}  // namespace
+}  // namespace abm
+
+using namespace abm;
+
+extern "C" size_t abm_sort_workspace_bytes(int64_t n) {
+    if (n < 0 || n > kMaxIndex) return 0;
+    return sort_ws_bytes(n);
+}
+
+extern "C" int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t descending,
+                               int32_t* perm, void* ws, size_t ws_bytes, void* stream) {
+    if (!dst) return fail(ABM_E_INVALID, "dst is NULL");
+    if (dst->n_attrs < 0 || dst->n_attrs > ABM_MAX_ATTRS)
+        return fail(ABM_E_INVALID, "n_attrs must be in [0, 16]");
+    if (dst->capacity < 0 || dst->capacity > kMaxIndex)
+        return fail(ABM_E_INVALID, "capacity must be in [0, 2^31)");
+    const int64_t n = dst->capacity;
+    if (n > 0 && !key) return fail(ABM_E_INVALID, "key is NULL");
+    for (int a = 0; a < dst->n_attrs; ++a)
+        if (n > 0 && !dst->attr[a]) return fail(ABM_E_INVALID, "attribute array is NULL");
+    int rc = check_device();
+    if (rc != ABM_OK) return rc;
+    rc = check_sort_ws(ws, ws_bytes, n);
+    if (rc != ABM_OK) return rc;
+    if (n == 0) return ABM_OK;
+    hipStream_t st = as_stream(stream);
+    SortWs s = carve_sort(ws, n);
+    PassArgs a{};
+    a.key = key;
+    a.counts = s.counts;
+    a.totals = s.totals;
+    a.base = s.base;
+    a.n = n;
+    a.n_tiles = tiles_of(n);
+    a.flip = descending ? ~0u : 0u;
+    uint32_t* kin = nullptr;
+    int32_t* vin = nullptr;
+    for (int pass = 0; pass < 4; ++pass) {
+        a.shift = 8u * uint32_t(pass);
+        a.in_key = kin;
+        a.in_val = vin;
+        a.out_key = (pass & 1) ? s.key_b : s.key_a;
+        a.out_val = (pass & 1) ? s.val_b : s.val_a;
+        if (pass == 0)
+            launch_pass<kFromKeys>(a, st);
+        else
+            launch_pass<kFromBuffer>(a, st);
+        kin = a.out_key;
+        vin = a.out_val;
+    }
+    // vin = the permutation: the agent now at position j was at vin[j]
+    for (int c = -1; c < dst->n_attrs; ++c) {
+        int32_t* col = c < 0 ? dst->alive : dst->attr[c];
+        if (!col) continue;
+        hipLaunchKernelGGL(k_gather, stream_grid(n), dim3(kBlock), 0, st, col, vin, s.stage, n);
+        hipLaunchKernelGGL(k_copy, stream_grid(n), dim3(kBlock), 0, st, s.stage, col, n);
+    }
+    if (perm) hipLaunchKernelGGL(k_copy, stream_grid(n), dim3(kBlock), 0, st, vin, perm, n);
+    return launch_status("sort_agents");
+}
+
+extern "C" int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order, int64_t* d_count,
+                                 void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || n > kMaxIndex) return fail(ABM_E_INVALID, "n must be in [0, 2^31)");
+    if (n > 0 && (!cond || !order)) return fail(ABM_E_INVALID, "cond or order is NULL");
+    if (!d_count) return fail(ABM_E_INVALID, "d_count is NULL");
+    int rc = check_device();
+    if (rc != ABM_OK) return rc;
+    rc = check_sort_ws(ws, ws_bytes, n);
+    if (rc != ABM_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    SortWs s = carve_sort(ws, n);
+    PassArgs a{};
+    a.cond = cond;
+    a.counts = s.counts;
+    a.totals = s.totals;
+    a.base = s.base;
+    a.n = n;
+    a.n_tiles = tiles_of(n > 0 ? n : 1);
+    a.out_val = order;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_count_out, dim3(1), dim3(64), 0, st, nullptr, d_count);
+        return launch_status("select_agents");
+    }
+    launch_pass<kFromCond>(a, st);
+    hipLaunchKernelGGL(k_count_out, dim3(1), dim3(64), 0, st, s.totals, d_count);
+    return launch_status("select_agents");
+}

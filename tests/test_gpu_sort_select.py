@@ -1,0 +1,81 @@
+"""GPU parity of sort_agents (stable LSD radix sort + gather) and
+select_agents (stable partition) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2508_16508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _keys(kind, n, g):
+    if kind == "full":
+        return g.integers(-2 ** 31, 2 ** 31, size=n, dtype=np.int64).astype(np.int32)
+    if kind == "few":
+        return g.integers(-3, 4, size=n).astype(np.int32)       # long runs of equal keys
+    if kind == "equal":
+        return np.full(n, 7, dtype=np.int32)
+    if kind == "sorted":
+        return np.sort(g.integers(-1000, 1000, size=n)).astype(np.int32)
+    if kind == "reversed":
+        return np.sort(g.integers(-1000, 1000, size=n))[::-1].astype(np.int32).copy()
+    if kind == "extremes":
+        return g.choice(np.array([-2 ** 31, -1, 0, 1, 2 ** 31 - 1], dtype=np.int32), size=n)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("n", [1, 100, 4096, 4097, 3 * 4096 + 17, 1 << 20])
+@pytest.mark.parametrize("kind", ["full", "few", "equal", "sorted", "reversed", "extremes"])
+@pytest.mark.parametrize("descending", [False, True])
+def test_sort_matches_oracle(abm, orc, n, kind, descending):
+    g = np.random.default_rng(n + len(kind) + descending)
+    key = _keys(kind, n, g)
+    attrs = W.int32_rows(n + 1, 3, n)
+    alive = (g.random(n) < 0.5).astype(np.int32)
+    eo, ea, ep = orc.sort_agents(attrs, key, descending=descending, alive=alive)
+    d_attrs = torch.from_numpy(attrs).cuda()
+    d_alive = torch.from_numpy(alive).cuda()
+    perm = abm.sort_agents(d_attrs, torch.from_numpy(key).cuda(), descending, alive=d_alive)
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy()[:n], ep)
+    assert np.array_equal(d_attrs.cpu().numpy(), eo)
+    assert np.array_equal(d_alive.cpu().numpy(), ea)
+
+
+def test_sort_microbench_size(abm, orc):
+    """2^24 agents x 8 attributes, full-range keys (the select_update
+    workload's collection)."""
+    n = 1 << 24
+    g = np.random.default_rng(24)
+    key = _keys("full", n, g)
+    attrs = W.int32_rows(5, 8, n)
+    _, _, ep = orc.sort_agents(attrs[:1], key)
+    d_attrs = torch.from_numpy(attrs).cuda()
+    perm = abm.sort_agents(d_attrs, torch.from_numpy(key).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), ep)
+    sample = g.integers(0, n, size=4096)
+    got = d_attrs.cpu().numpy()
+    assert np.array_equal(got[:, sample], attrs[:, ep[sample]])
+
+
+@pytest.mark.parametrize("n", [1, 64, 4097, 1 << 16, 1 << 24])
+@pytest.mark.parametrize("p", [0.0, 0.001, 0.5, 1.0])
+def test_select_agents_matches_oracle(abm, orc, n, p):
+    cond = W.bernoulli_mask(n + 7, p, n) if 0 < p < 1 else np.full(n, int(p), dtype=np.uint8)
+    eo, ec = orc.select_agents(cond)
+    order, count = abm.select_agents(torch.from_numpy(cond).cuda())
+    torch.cuda.synchronize()
+    assert int(count.item()) == ec
+    assert np.array_equal(order.cpu().numpy()[:n], eo)
+
+
+def test_sort_rejects_small_workspace_and_bad_counts(abm):
+    key = torch.zeros(5000, dtype=torch.int32, device="cuda")
+    attrs = torch.zeros((1, 5000), dtype=torch.int32, device="cuda")
+    small = abm.sort_workspace(100)
+    with pytest.raises(abm.AbmError):
+        abm.sort_agents(attrs, key, ws=small)
+    with pytest.raises(abm.AbmError):
+        abm.select_agents(torch.zeros(5000, dtype=torch.uint8, device="cuda"), ws=small)
