@@ -69,6 +69,29 @@ class PredStats(C.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class LobParams(C.Structure):
+    """Limit order book parameters (Sec. 5.3; the paper gives no values)."""
+    _fields_ = [("cap", C.c_int32), ("traders", C.c_int32), ("T_order", C.c_uint32),
+                ("spread", C.c_int32), ("max_qty", C.c_int32), ("expiry", C.c_int32),
+                ("price0", C.c_int32), ("seed", C.c_uint32)]
+
+
+class _LobState(C.Structure):
+    _fields_ = [("side", C.POINTER(C.c_int32)), ("price", C.POINTER(C.c_int32)),
+                ("qty", C.POINTER(C.c_int32)), ("time", C.POINTER(C.c_int32)),
+                ("alive", C.POINTER(C.c_int32)), ("last_price", C.c_int32),
+                ("step", C.c_uint32)]
+
+
+class LobStats(C.Structure):
+    _fields_ = [("buys", C.c_int64), ("sells", C.c_int64), ("placed", C.c_int64),
+                ("dropped", C.c_int64), ("expired", C.c_int64), ("volume", C.c_int64),
+                ("filled_orders", C.c_int64), ("price", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class TrafficParams(C.Structure):
     """Traffic CA parameters (Sec. 5.2; the paper gives no values)."""
     _fields_ = [("length", C.c_int32), ("T_green", C.c_uint32), ("T_spawn", C.c_uint32),
@@ -128,6 +151,10 @@ def _declare(L):
     L.orc_sort_agents.restype = None
     L.orc_select_agents.argtypes = [_P8, C.c_int64, _P32]
     L.orc_select_agents.restype = C.c_int64
+    L.orc_lob_init.argtypes = [C.POINTER(LobParams), C.POINTER(_LobState)]
+    L.orc_lob_init.restype = None
+    L.orc_lob_step.argtypes = [C.POINTER(LobParams), C.POINTER(_LobState), C.POINTER(LobStats)]
+    L.orc_lob_step.restype = None
     L.orc_traffic_init.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState)]
     L.orc_traffic_init.restype = None
     L.orc_traffic_step.argtypes = [C.POINTER(TrafficParams), C.POINTER(_TrafficState),
@@ -418,3 +445,48 @@ def traffic_step(P: TrafficParams, S: TrafficState) -> dict:
 
 def traffic_run(P: TrafficParams, S: TrafficState, n_steps: int) -> list:
     return [traffic_step(P, S) for _ in range(n_steps)]
+
+
+# ---------------------------------------------------------------- limit order books
+LOB_STATS = tuple(k for k, _ in LobStats._fields_)
+LOB_FIELDS = ("side", "price", "qty", "time", "alive")
+
+
+def lob_params(cap=1000, traders=10, T_order=2 ** 31, spread=20, max_qty=10, expiry=20,
+               price0=10000, seed=0) -> LobParams:
+    return LobParams(cap, traders, T_order, spread, max_qty, expiry, price0, seed)
+
+
+@dataclass
+class LobState:
+    """Host copy of one book: order slots and the last price."""
+    orders: dict
+    last_price: int
+    step: int = 0
+
+    def copy(self) -> "LobState":
+        return LobState({k: v.copy() for k, v in self.orders.items()}, self.last_price, self.step)
+
+    def _c(self):
+        return _LobState(*(_ptr(self.orders[k], C.c_int32) for k in LOB_FIELDS),
+                         self.last_price, self.step)
+
+
+def lob_init(P: LobParams) -> LobState:
+    S = LobState({k: np.zeros(P.cap, dtype=np.int32) for k in LOB_FIELDS}, 0)
+    cs = S._c()
+    lib().orc_lob_init(C.byref(P), C.byref(cs))
+    S.last_price, S.step = int(cs.last_price), int(cs.step)
+    return S
+
+
+def lob_step(P: LobParams, S: LobState) -> dict:
+    cs = S._c()
+    st = LobStats()
+    lib().orc_lob_step(C.byref(P), C.byref(cs), C.byref(st))
+    S.last_price, S.step = int(cs.last_price), int(cs.step)
+    return st.as_dict()
+
+
+def lob_run(P: LobParams, S: LobState, n_steps: int) -> list:
+    return [lob_step(P, S) for _ in range(n_steps)]

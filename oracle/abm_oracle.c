@@ -768,3 +768,180 @@ ORC_API int64_t orc_select_agents(const uint8_t* cond, int64_t n, int32_t* order
         if (!cond[i]) order[q++] = (int32_t)i;
     return p;
 }
+
+/* ------------------------------------------------------------------------- */
+/* 7. Limit order books with batch matching (Sec. 5.3, Fig. 5).                */
+/*                                                                           */
+/* Each book holds up to `cap` orders (agents: side, price, qty, time, alive)  */
+/* and a last price.  Step t of a book (draws keyed on (seed, t, trader,       */
+/* purpose)):                                                                 */
+/*   1. expiry: orders placed E or more steps ago are cancelled;              */
+/*   2. orders: trader k (0..K-1) places an order when draw(k, ORDER) <       */
+/*      T_order: a buy when draw(k, SIDE) < 2^31, else a sell, at price       */
+/*      last + u - D with u uniform on [0, 2D] (clamped to [1, 2^24 - 1]), for */
+/*      1 + (uniform on [0, Q)) shares; the new orders, in trader order, take */
+/*      the lowest free slots (add_agents); the ones that find none are       */
+/*      dropped;                                                               */
+/*   3. matching: buys in price-time priority (price descending, then time,  */
+/*      then slot), sells likewise with price ascending; CB and CS are the    */
+/*      cumulative shares along those lists; the matched volume is            */
+/*      V = max over buys r of min(CB_r, CS(p_r)), CS(p) = shares of the      */
+/*      sells priced at most p; the r-th buy fills clamp(V - CB_{r-1}, 0,     */
+/*      q_r) and each sell likewise; the new last price is the floor of the   */
+/*      mean of the buy price and the sell price covering share V;            */
+/*   4. filled orders are removed, partly filled ones keep the rest.          */
+/* ------------------------------------------------------------------------- */
+
+enum { P_L_ORDER = 0x40, P_L_SIDE = 0x41, P_L_PRICE = 0x42, P_L_QTY = 0x43 };
+#define LOB_MAX_PRICE ((1 << 24) - 1)
+
+typedef struct {
+    int32_t cap;           /* order slots per book */
+    int32_t traders;       /* K */
+    uint32_t T_order;      /* a trader orders when its draw < T_order */
+    int32_t spread;        /* D: price offsets on [-D, D] ticks */
+    int32_t max_qty;       /* Q: quantities on [1, Q] */
+    int32_t expiry;        /* E: an order lives E steps */
+    int32_t price0;        /* initial last price */
+    uint32_t seed;
+} orc_lob_params;
+
+typedef struct {
+    int32_t *side, *price, *qty, *time, *alive;   /* [cap]; side 0 buy, 1 sell */
+    int32_t last_price;
+    uint32_t step;
+} orc_lob_state;
+
+typedef struct {
+    int64_t buys, sells;      /* active after matching */
+    int64_t placed, dropped, expired;
+    int64_t volume, filled_orders;
+    int64_t price;
+} orc_lob_stats;
+
+ORC_API void orc_lob_init(const orc_lob_params* P, orc_lob_state* S)
+{
+    for (int32_t i = 0; i < P->cap; ++i) {
+        S->side[i] = 0; S->price[i] = 0; S->qty[i] = 0; S->time[i] = 0; S->alive[i] = 0;
+    }
+    S->last_price = P->price0;
+    S->step = 0;
+}
+
+/* price-time priority: does order a come before order b (same side)? */
+static int lob_before(const orc_lob_state* S, int32_t a, int32_t b)
+{
+    if (S->price[a] != S->price[b])
+        return S->side[a] == 0 ? S->price[a] > S->price[b] : S->price[a] < S->price[b];
+    if (S->time[a] != S->time[b]) return S->time[a] < S->time[b];
+    return a < b;
+}
+
+static const orc_lob_state* g_lob_sort_state;
+static int cmp_lob(const void* x, const void* y)
+{
+    int32_t a = *(const int32_t*)x, b = *(const int32_t*)y;
+    if (a == b) return 0;
+    return lob_before(g_lob_sort_state, a, b) ? -1 : 1;
+}
+
+ORC_API void orc_lob_step(const orc_lob_params* P, orc_lob_state* S, orc_lob_stats* st)
+{
+    const int32_t C = P->cap;
+    const uint32_t t = S->step;
+    orc_lob_stats loc;
+    memset(&loc, 0, sizeof loc);
+    uint8_t* kill = (uint8_t*)calloc((size_t)C, 1);
+    int32_t* buy = (int32_t*)malloc((size_t)C * sizeof(int32_t));
+    int32_t* sell = (int32_t*)malloc((size_t)C * sizeof(int32_t));
+    int64_t* cb = (int64_t*)malloc(((size_t)C + 1) * sizeof(int64_t));
+    int64_t* cs = (int64_t*)malloc(((size_t)C + 1) * sizeof(int64_t));
+
+    /* 1. expiry */
+    for (int32_t i = 0; i < C; ++i)
+        kill[i] = (uint8_t)(S->alive[i] && (int64_t)t - S->time[i] >= P->expiry);
+    orc_remove_agents(C, S->alive, kill, &loc.expired);
+
+    /* 2. new orders, in trader order, into the lowest free slots */
+    {
+        int32_t* rs = (int32_t*)malloc((size_t)(P->traders > 0 ? P->traders : 1) * 4 * sizeof(int32_t));
+        int32_t *r_side = rs, *r_price = rs + P->traders, *r_qty = rs + 2 * P->traders,
+                *r_time = rs + 3 * P->traders;
+        int64_t q = 0;
+        for (int32_t k = 0; k < P->traders; ++k) {
+            if (orc_rng(P->seed, t, (uint32_t)k, P_L_ORDER) >= P->T_order) continue;
+            int64_t price = (int64_t)S->last_price - P->spread +
+                            orc_uniform(orc_rng(P->seed, t, (uint32_t)k, P_L_PRICE),
+                                        (uint32_t)(2 * P->spread + 1));
+            if (price < 1) price = 1;
+            if (price > LOB_MAX_PRICE) price = LOB_MAX_PRICE;
+            r_side[q] = orc_rng(P->seed, t, (uint32_t)k, P_L_SIDE) < 0x80000000u ? 0 : 1;
+            r_price[q] = (int32_t)price;
+            r_qty[q] = 1 + (int32_t)orc_uniform(orc_rng(P->seed, t, (uint32_t)k, P_L_QTY),
+                                               (uint32_t)P->max_qty);
+            r_time[q] = (int32_t)t;
+            ++q;
+        }
+        int32_t* attr[4] = {S->side, S->price, S->qty, S->time};
+        const int32_t* rec[4] = {r_side, r_price, r_qty, r_time};
+        int64_t added = 0, dropped = 0;
+        orc_add_agents(C, 4, attr, S->alive, q, rec, &added, &dropped);
+        loc.placed = added;
+        loc.dropped = dropped;
+        free(rs);
+    }
+
+    /* 3. batch matching: both sides in priority order, cumulative shares */
+    int64_t nb = 0, ns = 0;
+    for (int32_t i = 0; i < C; ++i) {
+        if (!S->alive[i]) continue;
+        if (S->side[i] == 0) buy[nb++] = i; else sell[ns++] = i;
+    }
+    g_lob_sort_state = S;
+    qsort(buy, (size_t)nb, sizeof(int32_t), cmp_lob);
+    qsort(sell, (size_t)ns, sizeof(int32_t), cmp_lob);
+    cb[0] = 0; cs[0] = 0;
+    for (int64_t r = 0; r < nb; ++r) cb[r + 1] = cb[r] + S->qty[buy[r]];
+    for (int64_t r = 0; r < ns; ++r) cs[r + 1] = cs[r] + S->qty[sell[r]];
+    int64_t V = 0;
+    for (int64_t r = 0; r < nb; ++r) {
+        int64_t m = 0;                       /* sells priced at most the buy's price */
+        while (m < ns && S->price[sell[m]] <= S->price[buy[r]]) ++m;
+        int64_t v = cb[r + 1] < cs[m] ? cb[r + 1] : cs[m];
+        if (v > V) V = v;
+    }
+    loc.volume = V;
+    if (V > 0) {
+        int64_t rb = 0, rsl = 0;             /* the orders covering share V */
+        while (cb[rb + 1] < V) ++rb;
+        while (cs[rsl + 1] < V) ++rsl;
+        S->last_price = (int32_t)(((int64_t)S->price[buy[rb]] + S->price[sell[rsl]]) / 2);
+    }
+    /* 4. fills */
+    for (int i = 0; i < C; ++i) kill[i] = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int64_t n = s ? ns : nb;
+        const int32_t* list = s ? sell : buy;
+        const int64_t* cum = s ? cs : cb;
+        for (int64_t r = 0; r < n; ++r) {
+            int64_t f = V - cum[r];
+            if (f <= 0) break;
+            const int32_t i = list[r];
+            if (f >= S->qty[i]) { kill[i] = 1; f = S->qty[i]; }
+            else S->qty[i] -= (int32_t)f;
+            loc.filled_orders++;
+        }
+    }
+    {
+        int64_t removed = 0;
+        orc_remove_agents(C, S->alive, kill, &removed);
+    }
+    for (int32_t i = 0; i < C; ++i) {
+        if (!S->alive[i]) continue;
+        if (S->side[i] == 0) loc.buys++; else loc.sells++;
+    }
+    loc.price = S->last_price;
+    free(kill); free(buy); free(sell); free(cb); free(cs);
+    S->step += 1;
+    if (st) *st = loc;
+}
