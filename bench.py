@@ -241,6 +241,32 @@ def sort_select_leg(abm, torch, W, n=1 << 24, reps=5):
     return out
 
 
+def lob_leg(abm, torch, n_books=500, cap=1000, traders=100, steps=100):
+    """Limit order books (Sec. 5.3): n_books books of `cap` order slots with
+    `traders` noisy traders each, `steps` steps in one call (one workgroup per
+    book, the book in LDS, all books matched at once)."""
+    books = abm.OrderBooks(abm.lob_params(cap=cap, traders=traders, seed=1), n_books)
+    books.init()
+    books.run(20)                                  # warm-up: the books fill
+    stats = torch.zeros((steps, n_books, 8), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    books.run(steps, stats)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    orders = int((stats[:, :, 0] + stats[:, :, 1]).sum().item())
+    volume = int(stats[:, :, 5].sum().item())
+    del books, stats
+    return {"workload": f"{n_books} books of {cap} slots, {traders} traders each, {steps} steps "
+                        "in one call, orders with probability 1/2, spread 20 ticks, qty 1-10, "
+                        "expiry 20 steps", "steps": steps, "ms": ms,
+            "resting_orders_per_step": orders / steps, "shares_matched": volume,
+            "book_steps_per_s": n_books * steps / (ms / 1e3)}
+
+
 def traffic_leg(abm, torch, n_roads=500, length=100, steps=1000):
     """Traffic CA (Sec. 5.2): n_roads roads of 3 x length cells, `steps` steps in
     one call (one workgroup per road, the road held in LDS); car updates per
@@ -447,6 +473,7 @@ def main():
             "2048x2048 torus as above with prey matched by rank within each cell (the r-th "
             "wolf of a cell eats its r-th sheep), steps 1-999 after a warm-up step")
         out["traffic"] = traffic_leg(abm, torch)
+        out["lob"] = lob_leg(abm, torch)
         out["sort_select"] = sort_select_leg(abm, torch, W)
         out["batched"] = batched_leg(abm, W, torch)
         torch.cuda.empty_cache()

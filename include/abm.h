@@ -362,6 +362,56 @@ ABM_API int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order, in
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Limit order books with batch matching (Sec. 5.3, Fig. 5), many books at
+ * once (the paper vectorises the matching over books, Table 4).  A book holds
+ * up to cap orders (side 0 buy / 1 sell, price in ticks, qty, time = step
+ * placed, alive) and a last price.  Step t of book b, with draws keyed on
+ * (seed + b, t, trader, purpose):
+ *   expiry   orders placed expiry or more steps ago are cancelled;
+ *   orders   trader k < traders orders when its draw < T_order: a buy or a
+ *            sell with probability 1/2 each, at last + u - spread (u uniform
+ *            on [0, 2 spread], clamped to [1, 2^24 - 1]), for 1 + (uniform
+ *            on [0, max_qty)) shares; the new orders, in trader order, take
+ *            the lowest free slots; those finding none are dropped;
+ *   matching buys in price-time priority (price descending, then time, then
+ *            slot), sells with price ascending; CB, CS the cumulative shares
+ *            along those lists; matched volume V = max over buys r of
+ *            min(CB_r, CS(p_r)), CS(p) = shares of the sells priced at most
+ *            p; every order fills the part of its share range below V
+ *            (filled orders are removed, partly filled ones keep the rest);
+ *            the last price becomes the floor of the mean of the buy and sell
+ *            prices covering share V (unchanged when V = 0).
+ * ------------------------------------------------------------------------- */
+typedef struct abm_lob_params {
+    int32_t cap;           /* order slots per book, in [1, 1024] */
+    int32_t traders;       /* in [0, 1024] */
+    uint32_t T_order;      /* a trader orders when its draw < T_order */
+    int32_t spread;        /* price offsets on [-spread, spread] ticks, spread in [0, 2^22] */
+    int32_t max_qty;       /* quantities on [1, max_qty], max_qty in [1, 2^20] */
+    int32_t expiry;        /* an order lives expiry steps, >= 1 */
+    int32_t price0;        /* initial last price, in [1, 2^24) */
+    uint32_t seed;         /* book b draws with seed + b (mod 2^32) */
+} abm_lob_params;
+
+typedef struct abm_lob_state {
+    int32_t n_books;       /* in [1, 2^20] */
+    int32_t *side, *price, *qty, *time, *alive;   /* device int32[n_books * cap] */
+    int32_t* last_price;   /* device int32[n_books] */
+    int64_t* stats;        /* device int64[n_steps][n_books][8] or NULL: per step and book
+                              buys, sells (live after matching), placed, dropped, expired,
+                              volume, filled_orders (fully or partly), price */
+    uint32_t step;         /* (host) index of the next step; steps stay below 2^24 */
+} abm_lob_state;
+
+/* Empty books at price0; sets s->step = 0. */
+ABM_API int abm_lob_init(const abm_lob_params* p, abm_lob_state* s, void* stream);
+
+/* Run n_steps steps of every book from s->step, then advance s->step.  One
+ * workgroup per book keeps the book in LDS for the whole call. */
+ABM_API int abm_lob_step(const abm_lob_params* p, abm_lob_state* s, int32_t n_steps,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------
  * Traffic cellular automaton (Sec. 5.2, Fig. 4), many roads at once (the
  * paper vectorises it over roads with different car counts, Table 3).  A road
  * is 3 lanes x length cells; cell (lane, x), x = 0 the entry column, x =

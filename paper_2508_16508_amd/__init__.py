@@ -30,7 +30,8 @@ EXPORTED = (
     "abm_predation_batched_init", "abm_predation_run_batched", "abm_predation_batched_grass",
     "abm_select_update_batched", "abm_add_agents_batched", "abm_remove_agents_batched",
     "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
-    "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents",
+    "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents", "abm_lob_init",
+    "abm_lob_step",
 )
 
 
@@ -56,6 +57,18 @@ class PredationParams(C.Structure):
                 ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
                 ("cap_s", C.c_int64), ("cap_w", C.c_int64),
                 ("n_s0", C.c_int64), ("n_w0", C.c_int64), ("multi_prey", C.c_int32)]
+
+
+class LobParams(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("traders", C.c_int32), ("T_order", C.c_uint32),
+                ("spread", C.c_int32), ("max_qty", C.c_int32), ("expiry", C.c_int32),
+                ("price0", C.c_int32), ("seed", C.c_uint32)]
+
+
+class LobStatePtrs(C.Structure):
+    _fields_ = [("n_books", C.c_int32), ("side", C.c_void_p), ("price", C.c_void_p),
+                ("qty", C.c_void_p), ("time", C.c_void_p), ("alive", C.c_void_p),
+                ("last_price", C.c_void_p), ("stats", C.c_void_p), ("step", C.c_uint32)]
 
 
 class TrafficParams(C.Structure):
@@ -646,4 +659,50 @@ class TrafficRoads:
         st = self._ptrs(stats)
         _check(lib().abm_traffic_step(C.byref(self.params), C.byref(st), n_steps,
                                       _stream(stream)))
+        self.step = int(st.step)
+
+
+# ---------------------------------------------------------------- limit order books
+LOB_STAT_NAMES = ("buys", "sells", "placed", "dropped", "expired", "volume", "filled_orders",
+                  "price")
+LOB_FIELDS = ("side", "price", "qty", "time", "alive")
+
+
+def lob_params(cap=1000, traders=10, T_order=2 ** 31, spread=20, max_qty=10, expiry=20,
+               price0=10000, seed=0) -> LobParams:
+    """Noisy traders on limit order books (Sec. 5.3); prices in ticks."""
+    return LobParams(cap, traders, T_order, spread, max_qty, expiry, price0, seed)
+
+
+class OrderBooks:
+    """n_books books of one capacity, device-resident: order slots
+    (side, price, qty, time, alive) as int32 [n_books, cap] and the last price
+    per book; book b draws with seed + b."""
+
+    def __init__(self, params: LobParams, n_books: int, device="cuda"):
+        self.params = params
+        self.n_books = n_books
+        self.orders = {f: torch.zeros((n_books, params.cap), dtype=torch.int32, device=device)
+                       for f in LOB_FIELDS}
+        self.last_price = torch.zeros(n_books, dtype=torch.int32, device=device)
+        self.step = 0
+
+    def _ptrs(self, stats=None) -> LobStatePtrs:
+        return LobStatePtrs(self.n_books, *(self.orders[f].data_ptr() for f in LOB_FIELDS),
+                            self.last_price.data_ptr(),
+                            stats.data_ptr() if stats is not None else None, self.step)
+
+    def init(self, stream=None):
+        st = self._ptrs()
+        _check(lib().abm_lob_init(C.byref(self.params), C.byref(st), _stream(stream)))
+        self.step = int(st.step)
+
+    def run(self, n_steps: int, stats: torch.Tensor | None = None, stream=None):
+        """Advance every book n_steps; stats (int64 [n_steps, n_books, 8])
+        receives per-step counts (LOB_STAT_NAMES)."""
+        if stats is not None:
+            _require(stats, torch.int64, "stats")
+            assert stats.numel() >= 8 * n_steps * self.n_books
+        st = self._ptrs(stats)
+        _check(lib().abm_lob_step(C.byref(self.params), C.byref(st), n_steps, _stream(stream)))
         self.step = int(st.step)

@@ -125,7 +125,8 @@ def test_struct_layouts_match_header(abm, tmp_path):
                "abm_predation_params": abm.PredationParams, "abm_species": abm.SpeciesPtrs,
                "abm_predation_state": abm.PredationStatePtrs, "abm_model_desc": abm.ModelDesc,
                "abm_batch": abm.Batch, "abm_tuning": abm.Tuning,
-               "abm_traffic_params": abm.TrafficParams, "abm_traffic_state": abm.TrafficStatePtrs}
+               "abm_traffic_params": abm.TrafficParams, "abm_traffic_state": abm.TrafficStatePtrs,
+               "abm_lob_params": abm.LobParams, "abm_lob_state": abm.LobStatePtrs}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "abm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
