@@ -164,6 +164,9 @@ __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t digit, bool active
 template <int SRC>
 __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
     __shared__ uint32_t wcount[kWaves][kBins];   // running, then exclusive across waves
+    __shared__ uint32_t dstart[kBins];           // start of each digit within the tile
+    __shared__ uint32_t skey[kTile];             // the tile in digit order
+    __shared__ int32_t sval[kTile];
     const uint32_t t = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int bits = SRC == kFromCond ? 1 : 8;
@@ -191,25 +194,65 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // exclusive offsets of the waves within each digit of the tile
-    for (int d = threadIdx.x; d < kBins; d += kBlock) {
-        uint32_t run = 0;
+    // per digit: exclusive offsets of the waves, and the digit's tile total
+    uint32_t dtot = 0;
+    if (threadIdx.x < kBins) {
+        const int d = threadIdx.x;
         for (int q = 0; q < kWaves; ++q) {
             const uint32_t c = wcount[q][d];
-            wcount[q][d] = run;
-            run += c;
+            wcount[q][d] = dtot;
+            dtot += c;
         }
     }
+    // exclusive scan of the digit totals: where each digit starts in the tile
+    {
+        uint32_t x = dtot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        __shared__ uint32_t wtot[kWaves];
+        if (lane == 63) wtot[w] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int q = 0; q < w; ++q) before += wtot[q];
+        if (threadIdx.x < kBins) dstart[threadIdx.x] = before + x - dtot;
+    }
     __syncthreads();
+    if (SRC == kFromCond) {
+        // two digits only: each lane's run is already contiguous, write directly
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int64_t i = slot_of(t, w, k, lane);
+            if (i >= a.n) continue;
+            const uint32_t d = dig[k];
+            a.out_val[int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] + wcount[w][d] +
+                      rank[k]] = val[k];
+        }
+        return;
+    }
+    // stage the tile in digit order
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int64_t i = slot_of(t, w, k, lane);
         if (i >= a.n) continue;
         const uint32_t d = dig[k];
+        const uint32_t p = dstart[d] + wcount[w][d] + rank[k];
+        skey[p] = (SRC == kFromCond) ? d : key[k];
+        sval[p] = val[k];
+    }
+    __syncthreads();
+    // consecutive threads write consecutive positions of a digit's run
+    const int64_t left = a.n - int64_t(t) * kTile;
+    const int32_t n_tile = left < kTile ? int32_t(left) : int32_t(kTile);
+    for (int32_t p = threadIdx.x; p < n_tile; p += kBlock) {
+        const uint32_t kk = skey[p];
+        const uint32_t d = (SRC == kFromCond) ? kk : ((kk >> a.shift) & 0xFFu);
         const int64_t dst = int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] +
-                            wcount[w][d] + rank[k];
-        if (SRC != kFromCond) a.out_key[dst] = key[k];
-        a.out_val[dst] = val[k];
+                            (p - int32_t(dstart[d]));
+        if (SRC != kFromCond) a.out_key[dst] = kk;
+        a.out_val[dst] = sval[p];
     }
 }
 
