@@ -518,6 +518,9 @@ __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
             // every member has read the mailbox before the leader writes it again
             if (!team_sync(tm)) return;
             const int32_t m = s_model;
+            // every wave has read s_model before thread 0 reuses it (the solo
+            // loop below writes it straight away)
+            __syncthreads();
             if (m < 0) break;
             if (!run_model<ITEMS>(a, m, tm, lds)) return;
         }
