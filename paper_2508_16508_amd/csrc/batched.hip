@@ -92,6 +92,30 @@ __device__ __forceinline__ uint32_t block_sum32(uint32_t v, uint32_t* lds) {
     return s;
 }
 
+// Block-wide inclusive scan of one value per thread: *incl gets this thread's
+// inclusive prefix, the return value the block total.  lds holds one word per
+// wave.
+__device__ __forceinline__ uint32_t block_incl_scan32(uint32_t v, uint32_t* lds, uint32_t* incl) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+        const uint32_t s = lds[w];
+        before += w < wave ? s : 0u;
+        all += s;
+    }
+    *incl = before + x;
+    return all;
+}
+
 // Block-wide exclusive ranks of ITEMS flags per lane over one chunk (slot
 // order = wave, item, lane); returns the chunk total.  lds holds one word per
 // wave.  Two barriers.
@@ -155,6 +179,7 @@ struct Team {
     uint64_t* err;
     int32_t* s_pre;             // LDS: breeder prefixes [2][kMaxTeam + 1], free prefix [2], live
     int32_t* s_ok;              // LDS: barrier outcome
+    int32_t* s_bound;           // LDS: [2][kMaxTeam + 1] member range bounds of this launch
 };
 
 __device__ __forceinline__ int32_t* member_list(const Team& tm, int j) {
@@ -212,14 +237,21 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t chunk = int32_t(blockDim.x) * ITEMS;
     const int32_t lbase = wave * ITEMS * 64 + lane;
-    // this member's slot range of each species; species 1's list follows species 0's
+    // this member's slot range of each species (the whole model when alone, the
+    // launch's balanced bounds in a team); species 1's list follows species 0's
     int32_t lo[2], hi[2];
-    const int32_t per0 = (v.cap[0] + tm.K - 1) / tm.K;
-    const int32_t per1 = (v.cap[1] + tm.K - 1) / tm.K;
-    lo[0] = min(v.cap[0], tm.r * per0);
-    hi[0] = min(v.cap[0], lo[0] + per0);
-    lo[1] = min(v.cap[1], tm.r * per1);
-    hi[1] = min(v.cap[1], lo[1] + per1);
+    if (tm.K == 1) {
+        lo[0] = 0;
+        hi[0] = v.cap[0];
+        lo[1] = 0;
+        hi[1] = v.cap[1];
+    } else {
+        lo[0] = tm.s_bound[tm.r];
+        hi[0] = tm.s_bound[tm.r + 1];
+        lo[1] = tm.s_bound[kMaxTeam + 1 + tm.r];
+        hi[1] = tm.s_bound[kMaxTeam + 1 + tm.r + 1];
+    }
+    const int32_t list1 = v.cap[0];
     int32_t* my_list = member_list(tm, tm.r);
 
     // ---- A: move + claims
@@ -266,7 +298,7 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         uint32_t base_rank = 0, nfree = 0;
-        int32_t* list = my_list + (s ? per0 : 0);
+        int32_t* list = my_list + (s ? list1 : 0);
         for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
@@ -372,7 +404,7 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
     for (int s = 0; s < 2; ++s) {
         const int32_t* bpre = s ? bpre1 : bpre0;
         const uint32_t nb = uint32_t(bpre[tm.K]);
-        const int32_t list_off = s ? per0 : 0;
+        const int32_t list_off = s ? list1 : 0;
         uint32_t base_rank = uint32_t(fpre[s]);
         for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
             int32_t al[ITEMS];
@@ -453,6 +485,81 @@ __device__ ModelView view_of(const BatchArgs& a, const abm_model_desc* d) {
     return v;
 }
 
+// Member ranges of a team for one launch, balanced by work: the members count
+// the live agents of every 4096-slot block of their share of the model, and
+// then every member computes the same bounds from the block costs (a slot
+// costs 1 and a live agent 3 more: a dead slot is one coalesced load per pass,
+// a live agent a draw, several gathers and atomics).  The live agents sit in
+// the lowest slots (children take the lowest free slots), so equal slot
+// counts would leave a few members with all the work.  False if a team barrier
+// failed.
+constexpr int32_t kBalBlock = 4096;
+
+template <int ITEMS>
+__device__ bool balance_team(const ModelView& v, Team& tm, uint32_t* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t chunk = int32_t(blockDim.x) * ITEMS;
+    const int32_t lbase = wave * ITEMS * 64 + lane;
+    int32_t* cost = member_list(tm, 0);   // lists are idle until the first step
+    int32_t nblk[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) nblk[s] = (v.cap[s] + kBalBlock - 1) / kBalBlock;
+    // live agents per block, each member over its share of the blocks
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int32_t per = (nblk[s] + tm.K - 1) / tm.K;
+        const int32_t b0 = min(nblk[s], tm.r * per), b1 = min(nblk[s], b0 + per);
+        for (int32_t blk = b0; blk < b1; ++blk) {
+            const int32_t lo = blk * kBalBlock, hi = min(v.cap[s], lo + kBalBlock);
+            uint32_t live = 0;
+            for (int32_t c0 = lo; c0 < hi; c0 += chunk) {
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k) {
+                    const int32_t i = c0 + lbase + k * 64;
+                    live += (i < hi && v.al[s][i] != 0) ? 1u : 0u;
+                }
+            }
+            live = block_sum32(live, lds);
+            if (threadIdx.x == 0) cost[(s ? nblk[0] : 0) + blk] = (hi - lo) + 3 * int32_t(live);
+        }
+    }
+    if (!team_sync(tm)) return false;
+    // bounds: member r starts at the first block whose cost prefix reaches
+    // r / K of the total
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int32_t* c = cost + (s ? nblk[0] : 0);
+        int32_t* bound = tm.s_bound + s * (kMaxTeam + 1);
+        uint32_t total = 0;
+        for (int32_t b = threadIdx.x; b < nblk[s]; b += blockDim.x) total += uint32_t(c[b]);
+        total = block_sum32(total, lds);
+        if (threadIdx.x <= tm.K) bound[threadIdx.x] = threadIdx.x == 0 ? 0 : v.cap[s];
+        __syncthreads();
+        uint32_t carry = 0;
+        for (int32_t b0 = 0; b0 < nblk[s]; b0 += int32_t(blockDim.x)) {
+            const int32_t b = b0 + int32_t(threadIdx.x);
+            const uint32_t mine = b < nblk[s] ? uint32_t(c[b]) : 0u;
+            uint32_t incl;
+            const uint32_t chunk_total = block_incl_scan32(mine, lds, &incl);
+            const uint32_t before = carry + incl - mine;
+            // the block where the prefix first reaches r * total / K
+            for (int r = 1; r < tm.K; ++r) {
+                const uint64_t target = (uint64_t(total) * uint32_t(r) + uint32_t(tm.K) - 1) /
+                                        uint32_t(tm.K);
+                if (b < nblk[s] && before < target && target <= before + mine)
+                    bound[r] = min(v.cap[s], (b + 1) * kBalBlock);
+            }
+            carry += chunk_total;
+        }
+        __syncthreads();
+        // bounds must not decrease (empty members keep a zero-width range)
+        if (threadIdx.x == 0)
+            for (int r = 1; r <= tm.K; ++r) bound[r] = max(bound[r], bound[r - 1]);
+        __syncthreads();
+    }
+    return true;
+}
+
 // Runs model m's pending steps (at most max_steps) with team tm; member 0
 // updates the descriptor.  False if a team barrier failed.
 template <int ITEMS>
@@ -468,6 +575,7 @@ __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds
     const int32_t t0 = d->step;
     int32_t t1 = d->steps_target;
     if (t1 - t0 > a.max_steps) t1 = t0 + a.max_steps;
+    if (tm.K > 1 && t1 > t0 && !balance_team<ITEMS>(v, tm, lds)) return false;
     uint64_t updates = 0;
     for (int32_t t = t0; t < t1; ++t) {
         uint32_t live;
@@ -489,6 +597,7 @@ __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
     __shared__ uint32_t lds[16];
     __shared__ int32_t s_pre[2 * (kMaxTeam + 1) + 3];
     __shared__ int32_t s_ok, s_model;
+    __shared__ int32_t s_bound[2 * (kMaxTeam + 1)];
     const uint32_t b = blockIdx.x;
     Team tm;
     tm.gen = 0;
@@ -498,6 +607,7 @@ __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
     tm.err = a.err;
     tm.s_pre = s_pre;
     tm.s_ok = &s_ok;
+    tm.s_bound = s_bound;
     if (b < a.team_wgs) {
         const uint32_t xcd = b % 8, idx = b / 8;
         const uint32_t team = xcd + 8 * (idx / a.team_k);

@@ -167,9 +167,12 @@ class Scheduler:
 
     def chunk_target(self, r: Running) -> int:
         """Steps this model may advance in the next chunk: a budget of slot-steps
-        split by the model's slot count, so small models run many steps and
-        large ones few, and a chunk's duration stays bounded."""
-        k = max(1, self.budget // (r.req.cap_s + r.req.cap_w))
+        per workgroup, split by the model's slot count, so small models run many
+        steps and large ones few, and a chunk's duration stays bounded.  A model
+        advanced by a team of workgroups (runner.workgroups_for) gets the budget
+        of every member."""
+        wg = self.runner.workgroups_for(r) if hasattr(self.runner, "workgroups_for") else 1
+        k = max(1, self.budget * wg // (r.req.cap_s + r.req.cap_w))
         return min(r.req.steps, r.step + k)
 
     def serve(self, requests) -> Report:
@@ -236,7 +239,7 @@ class GpuRunner:
 
     def __init__(self, cell_capacity, sheep_capacity, wolf_capacity, max_active=4096,
                  block_threads=512, items=4, device="cuda", keep_results=False,
-                 max_model_cap=None, team_size=1, team_min_size=1 << 18):
+                 max_model_cap=None, team_size=4, team_min_size=1 << 18):
         import torch
 
         import paper_2508_16508_amd as abm
@@ -266,6 +269,13 @@ class GpuRunner:
         self.keep_results = keep_results
         self.results = {}
         self.device = device
+
+    def _team_model(self, r) -> bool:
+        return self.team_size > 1 and r.req.cells + r.req.cap_s + r.req.cap_w >= self.team_min_size
+
+    def workgroups_for(self, r) -> int:
+        """Workgroups that will advance model r (a team, or one)."""
+        return self.team_size if self._team_model(r) else 1
 
     def _descs(self, models, targets):
         abm = self.abm
@@ -305,7 +315,7 @@ class GpuRunner:
         order = np.argsort(-np.asarray(size), kind="stable").astype(np.int32)
         self.order[:n].copy_(torch.from_numpy(order))
         b = self._batch(self.desc, n)
-        n_team = sum(1 for v in size if v >= self.team_min_size) if self.team_size > 1 else 0
+        n_team = sum(1 for r in models if self._team_model(r))
         t = abm.Tuning(self.block_threads, self.workgroups, self.items, self.team_size, n_team, 0)
         abm._check(abm.lib().abm_predation_run_batched(C.byref(b), abm._p(self.order), 1 << 30,
                                                        C.byref(t), abm._p(self.ws),

@@ -122,3 +122,20 @@ def test_request_that_can_never_fit_is_rejected():
     sch = Scheduler(FakeRunner(clock), 100, 100, 100, clock=clock, sleep=clock.sleep)
     with pytest.raises(ValueError):
         sch.serve([Request(0, 0.0, 32, 10, 0)])
+
+
+def test_team_models_get_the_budget_of_every_member():
+    clock = FakeClock()
+
+    class TeamRunner(FakeRunner):
+        def workgroups_for(self, r):
+            return 4 if r.req.side >= 500 else 1
+
+    run = TeamRunner(clock)
+    sch = Scheduler(run, 10 ** 8, 10 ** 8, 10 ** 8, slot_step_budget=1 << 22, clock=clock,
+                    sleep=clock.sleep)
+    big, small = Request(0, 0.0, 600, 5000, 1), Request(1, 0.0, 300, 5000, 2)
+    from paper_2508_16508_amd.serve import Running
+    rb, rs = Running(big, 0, 0, 0, 0.0), Running(small, 0, 0, 0, 0.0)
+    assert sch.chunk_target(rb) == (4 << 22) // (big.cap_s + big.cap_w)
+    assert sch.chunk_target(rs) == (1 << 22) // (small.cap_s + small.cap_w)
