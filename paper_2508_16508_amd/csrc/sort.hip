@@ -3,7 +3,8 @@
 //
 // sort_agents is a least-significant-digit radix sort of (key, slot) pairs
 // with 8-bit digits, four passes over 32-bit keys, followed by a gather of
-// every attribute column through the resulting permutation.  Each pass is
+// every attribute column through the resulting permutation (up to four
+// columns at a time, packed into one record per agent).  Each pass is
 //   histogram  per 4096-key tile, 256 bins in LDS, stored digit-major;
 //   scan       one workgroup per digit scans that digit's tile counts (the
 //              tile's offset within the digit's bucket), and one workgroup
@@ -21,8 +22,9 @@
 // and then all bits flipped (descending), so the descending sort keeps equal
 // keys in index order too.
 //
-// select_agents is one such pass on a 1-bit digit (0 for agents that satisfy
-// the condition): a stable partition whose permutation is the index list.
+// select_agents is a stable partition, set flags first: a count of the set flags
+// per 4096-flag tile, one scan of the tile counts, and a pass that stages
+// each tile's indices in partition order in LDS and writes both runs.
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -40,13 +42,11 @@ constexpr int kBins = 256;
 
 enum KeySource : int {
     kFromKeys = 0,      // first pass: int32 keys, slot = index
-    kFromBuffer = 1,    // later passes: (ukey, slot) ping-pong buffers
-    kFromCond = 2       // select_agents: digit = (cond == 0)
+    kFromBuffer = 1     // later passes: (ukey, slot) ping-pong buffers
 };
 
 struct PassArgs {
     const int32_t* key;        // kFromKeys
-    const uint8_t* cond;       // kFromCond
     const uint32_t* in_key;    // kFromBuffer
     const int32_t* in_val;
     uint32_t* out_key;
@@ -72,14 +72,10 @@ __device__ __forceinline__ void load_item(const PassArgs& a, int64_t i, uint32_t
         ukey = (uint32_t(a.key[i]) ^ 0x80000000u) ^ a.flip;
         val = int32_t(i);
         digit = (ukey >> a.shift) & 0xFFu;
-    } else if (SRC == kFromBuffer) {
+    } else {
         ukey = a.in_key[i];
         val = a.in_val[i];
         digit = (ukey >> a.shift) & 0xFFu;
-    } else {
-        ukey = 0;
-        val = int32_t(i);
-        digit = a.cond[i] ? 0u : 1u;
     }
 }
 
@@ -154,6 +150,7 @@ __global__ __launch_bounds__(kBins) void k_digit_base(PassArgs a) {
 // Lanes of the wave whose digit equals this lane's (among the active lanes).
 __device__ __forceinline__ uint64_t same_digit_lanes(uint32_t digit, bool active, int bits) {
     uint64_t m = __ballot(active);
+#pragma unroll
     for (int b = 0; b < bits; ++b) {
         const uint64_t set = __ballot(active && ((digit >> b) & 1u));
         m &= ((digit >> b) & 1u) ? set : ~set;
@@ -169,7 +166,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
     __shared__ int32_t sval[kTile];
     const uint32_t t = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int bits = SRC == kFromCond ? 1 : 8;
     for (int d = threadIdx.x; d < kWaves * kBins; d += kBlock) (&wcount[0][0])[d] = 0;
     __syncthreads();
     uint32_t key[kItems], dig[kItems], rank[kItems];
@@ -183,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
         val[k] = 0;
         dig[k] = 0;
         if (active) load_item<SRC>(a, i, key[k], val[k], dig[k]);
-        const uint64_t peers = same_digit_lanes(dig[k], active, bits);
+        const uint64_t peers = same_digit_lanes(dig[k], active, 8);
         // the lowest peer reads and advances the wave's counter for this digit
         const uint32_t before = active ? wcount[w][dig[k]] : 0u;
         rank[k] = before + uint32_t(__popcll(peers & below));
@@ -220,18 +216,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
         if (threadIdx.x < kBins) dstart[threadIdx.x] = before + x - dtot;
     }
     __syncthreads();
-    if (SRC == kFromCond) {
-        // two digits only: each lane's run is already contiguous, write directly
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            const int64_t i = slot_of(t, w, k, lane);
-            if (i >= a.n) continue;
-            const uint32_t d = dig[k];
-            a.out_val[int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] + wcount[w][d] +
-                      rank[k]] = val[k];
-        }
-        return;
-    }
     // stage the tile in digit order
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -239,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
         if (i >= a.n) continue;
         const uint32_t d = dig[k];
         const uint32_t p = dstart[d] + wcount[w][d] + rank[k];
-        skey[p] = (SRC == kFromCond) ? d : key[k];
+        skey[p] = key[k];
         sval[p] = val[k];
     }
     __syncthreads();
@@ -248,21 +232,98 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
     const int32_t n_tile = left < kTile ? int32_t(left) : int32_t(kTile);
     for (int32_t p = threadIdx.x; p < n_tile; p += kBlock) {
         const uint32_t kk = skey[p];
-        const uint32_t d = (SRC == kFromCond) ? kk : ((kk >> a.shift) & 0xFFu);
+        const uint32_t d = (kk >> a.shift) & 0xFFu;
         const int64_t dst = int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] +
                             (p - int32_t(dstart[d]));
-        if (SRC != kFromCond) a.out_key[dst] = kk;
+        a.out_key[dst] = kk;
         a.out_val[dst] = sval[p];
     }
 }
 
-// out[j] = col[perm[j]]
-__global__ __launch_bounds__(kBlock) void k_gather(const int32_t* __restrict__ col,
-                                                   const int32_t* __restrict__ perm,
-                                                   int32_t* __restrict__ out, int64_t n) {
-    for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < n;
-         j += int64_t(gridDim.x) * kBlock)
-        out[j] = col[perm[j]];
+dim3 stream_grid(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return dim3(uint32_t(b < 8192 ? (b > 0 ? b : 1) : 8192));
+}
+
+// The columns go through the permutation in groups of up to kGatherCols:
+// the group is first packed into one record per agent (pack: coalesced), so
+// the gather makes one random read of a 4/8/16-byte record per agent instead
+// of one random 4-byte read per column.  Random reads, not bytes, bound a
+// gather: each costs a whole memory sector whatever its width.
+constexpr int kGatherCols = 4;
+
+template <int G> struct Rec;
+template <> struct Rec<1> { using T = int32_t; };
+template <> struct Rec<2> { using T = int2; };
+template <> struct Rec<3> { using T = int4; };
+template <> struct Rec<4> { using T = int4; };
+
+__device__ __forceinline__ int32_t field(int32_t r, int) { return r; }
+__device__ __forceinline__ int32_t field(const int2& r, int c) { return c == 0 ? r.x : r.y; }
+__device__ __forceinline__ int32_t field(const int4& r, int c) {
+    return c == 0 ? r.x : (c == 1 ? r.y : (c == 2 ? r.z : r.w));
+}
+__device__ __forceinline__ void set_field(int32_t& r, int, int32_t v) { r = v; }
+__device__ __forceinline__ void set_field(int2& r, int c, int32_t v) { (c == 0 ? r.x : r.y) = v; }
+__device__ __forceinline__ void set_field(int4& r, int c, int32_t v) {
+    (c == 0 ? r.x : (c == 1 ? r.y : (c == 2 ? r.z : r.w))) = v;
+}
+
+struct GatherArgs {
+    int32_t* col[kGatherCols];   // the group's columns (read by pack, written by gather)
+    void* rec;                   // n records
+    const int32_t* perm;
+    int64_t n;
+};
+
+// rec[i] = (col[0][i], ..., col[G-1][i])
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pack_cols(GatherArgs g) {
+    using T = typename Rec<G>::T;
+    T* rec = static_cast<T*>(g.rec);
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < g.n;
+         i += int64_t(gridDim.x) * kBlock) {
+        T r{};
+#pragma unroll
+        for (int c = 0; c < G; ++c) set_field(r, c, g.col[c][i]);
+        rec[i] = r;
+    }
+}
+
+// col[c][j] = rec[perm[j]].c.  A thread takes four consecutive j (one
+// 16-byte load of perm), so four random record reads are in flight at once.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_gather_recs(GatherArgs g) {
+    using T = typename Rec<G>::T;
+    const T* rec = static_cast<const T*>(g.rec);
+    const int64_t n4 = g.n >> 2;
+    const int4* perm4 = reinterpret_cast<const int4*>(g.perm);
+    for (int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x; q < n4;
+         q += int64_t(gridDim.x) * kBlock) {
+        const int4 p = perm4[q];
+        const T r0 = rec[p.x], r1 = rec[p.y], r2 = rec[p.z], r3 = rec[p.w];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            int32_t* out = g.col[c] + 4 * q;
+            out[0] = field(r0, c);
+            out[1] = field(r1, c);
+            out[2] = field(r2, c);
+            out[3] = field(r3, c);
+        }
+    }
+    // the last n mod 4 positions
+    if (blockIdx.x == 0)
+        for (int64_t j = 4 * n4 + threadIdx.x; j < g.n; j += kBlock) {
+            const T r = rec[g.perm[j]];
+#pragma unroll
+            for (int c = 0; c < G; ++c) g.col[c][j] = field(r, c);
+        }
+}
+
+template <int G>
+void gather_group(const GatherArgs& ga, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_cols<G>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
+    hipLaunchKernelGGL(k_gather_recs<G>, stream_grid((ga.n + 3) / 4), dim3(kBlock), 0, st, ga);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src,
@@ -270,6 +331,121 @@ __global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src
     for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < n;
          j += int64_t(gridDim.x) * kBlock)
         dst[j] = src[j];
+}
+
+// ---- select_agents: a stable partition, trues first.  A tile is 4096
+// flags, 16 per lane (one 16-byte load when the flags are 16-byte aligned).
+constexpr int kSelPerLane = 16;
+constexpr int64_t kSelTile = int64_t(kBlock) * kSelPerLane;
+
+// Bit b set when flag first + b is in range and nonzero.
+template <bool ALIGNED>
+__device__ __forceinline__ uint32_t load_flags(const uint8_t* __restrict__ cond, int64_t first,
+                                               int64_t n) {
+    uint32_t bits = 0;
+    if (ALIGNED && first + kSelPerLane <= n) {
+        const uint4 v = *reinterpret_cast<const uint4*>(cond + first);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                bits |= ((w[q] >> (8 * b)) & 0xFFu) ? (1u << (4 * q + b)) : 0u;
+    } else {
+        for (int b = 0; b < kSelPerLane; ++b)
+            if (first + b < n && cond[first + b]) bits |= 1u << b;
+    }
+    return bits;
+}
+
+// Exclusive scan of v over the workgroup (kBlock threads); *total = the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wtot[kWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        before += q < w ? wtot[q] : 0u;
+        all += wtot[q];
+    }
+    *total = all;
+    return before + x - v;
+}
+
+// counts[t] = flags set in tile t
+template <bool ALIGNED>
+__global__ __launch_bounds__(kBlock) void k_sel_count(const uint8_t* __restrict__ cond, int64_t n,
+                                                      uint32_t* __restrict__ counts) {
+    const int64_t first = int64_t(blockIdx.x) * kSelTile + int64_t(threadIdx.x) * kSelPerLane;
+    uint32_t total;
+    block_excl_scan(uint32_t(__popc(load_flags<ALIGNED>(cond, first, n))), &total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// counts[t] = the set flags before tile t (exclusive scan); totals[0] = all.
+// One workgroup.
+__global__ __launch_bounds__(kBlock) void k_sel_scan(uint32_t* counts, uint32_t n_tiles,
+                                                     uint32_t* totals) {
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < n_tiles; c0 += kBlock) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t v = i < n_tiles ? counts[i] : 0u;
+        uint32_t all;
+        const uint32_t ex = block_excl_scan(v, &all);
+        if (i < n_tiles) counts[i] = carry + ex;
+        carry += all;
+        __syncthreads();   // wtot is reused by the next chunk
+    }
+    if (threadIdx.x == 0) totals[0] = carry;
+}
+
+// The tile's set flags go to [counts[t], ...) and its clear flags to
+// [total + (t * 4096 - counts[t]), ...), both in index order; the tile is
+// staged in LDS in that order so that consecutive threads write consecutive
+// positions.
+template <bool ALIGNED>
+__global__ __launch_bounds__(kBlock) void k_sel_scatter(const uint8_t* __restrict__ cond,
+                                                        int64_t n,
+                                                        const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ totals,
+                                                        int32_t* __restrict__ order,
+                                                        int64_t* d_count) {
+    __shared__ int32_t sidx[kSelTile];
+    const uint32_t t = blockIdx.x;
+    const int64_t tile0 = int64_t(t) * kSelTile;
+    const int64_t first = tile0 + int64_t(threadIdx.x) * kSelPerLane;
+    const uint32_t bits = load_flags<ALIGNED>(cond, first, n);
+    uint32_t n_set;
+    const uint32_t set_before = block_excl_scan(uint32_t(__popc(bits)), &n_set);
+    const int64_t left = n - tile0;
+    const int32_t n_tile = left < kSelTile ? int32_t(left) : int32_t(kSelTile);
+    const int32_t lane0 = int32_t(threadIdx.x) * kSelPerLane;
+    const int32_t valid_before = lane0 < n_tile ? lane0 : n_tile;
+    uint32_t s_pos = set_before;
+    uint32_t c_pos = n_set + uint32_t(valid_before) - set_before;
+    for (int b = 0; b < kSelPerLane; ++b) {
+        if (lane0 + b >= n_tile) break;
+        const int32_t i = int32_t(first + b);
+        if ((bits >> b) & 1u)
+            sidx[s_pos++] = i;
+        else
+            sidx[c_pos++] = i;
+    }
+    __syncthreads();
+    const int64_t total = int64_t(totals[0]);
+    const int64_t set0 = int64_t(counts[t]);
+    const int64_t clear0 = total + (tile0 - set0) - int64_t(n_set);
+    for (int32_t p = threadIdx.x; p < n_tile; p += kBlock)
+        order[(p < int32_t(n_set) ? set0 : clear0) + p] = sidx[p];
+    if (t == 0 && threadIdx.x == 0) *d_count = total;
 }
 
 __global__ void k_count_out(const uint32_t* totals, int64_t* d_count) {
@@ -299,10 +475,12 @@ SortWs carve_sort(void* ws, int64_t n) {
         return q;
     };
     SortWs s;
+    // val_b (the final permutation) first: key_a .. stage are then one
+    // contiguous run of at least 16m bytes, which holds m 16-byte records
+    s.val_b = reinterpret_cast<int32_t*>(take(4 * m));
     s.key_a = reinterpret_cast<uint32_t*>(take(4 * m));
     s.key_b = reinterpret_cast<uint32_t*>(take(4 * m));
     s.val_a = reinterpret_cast<int32_t*>(take(4 * m));
-    s.val_b = reinterpret_cast<int32_t*>(take(4 * m));
     s.stage = reinterpret_cast<int32_t*>(take(4 * m));
     s.counts = reinterpret_cast<uint32_t*>(take(4 * int64_t(kBins) * tiles_of(m)));
     s.totals = reinterpret_cast<uint32_t*>(take(4 * kBins));
@@ -316,11 +494,6 @@ void launch_pass(const PassArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_digit_scan, dim3(kBins), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_digit_base, dim3(1), dim3(kBins), 0, st, a);
     hipLaunchKernelGGL(k_scatter<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
-}
-
-dim3 stream_grid(int64_t n) {
-    const int64_t b = (n + kBlock - 1) / kBlock;
-    return dim3(uint32_t(b < 8192 ? (b > 0 ? b : 1) : 8192));
 }
 
 int check_sort_ws(void* ws, size_t ws_bytes, int64_t n) {
@@ -385,12 +558,28 @@ extern "C" int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t d
         kin = a.out_key;
         vin = a.out_val;
     }
-    // vin = the permutation: the agent now at position j was at vin[j]
+    // vin = the permutation: the agent now at position j was at vin[j].  The
+    // columns go through it in groups of up to four, packed into records in
+    // the buffers the passes no longer need (vin is val_b).
+    int32_t* cols[ABM_MAX_ATTRS + 1];
+    int n_cols = 0;
     for (int c = -1; c < dst->n_attrs; ++c) {
         int32_t* col = c < 0 ? dst->alive : dst->attr[c];
-        if (!col) continue;
-        hipLaunchKernelGGL(k_gather, stream_grid(n), dim3(kBlock), 0, st, col, vin, s.stage, n);
-        hipLaunchKernelGGL(k_copy, stream_grid(n), dim3(kBlock), 0, st, s.stage, col, n);
+        if (col) cols[n_cols++] = col;
+    }
+    for (int c0 = 0; c0 < n_cols; c0 += kGatherCols) {
+        const int g = n_cols - c0 < kGatherCols ? n_cols - c0 : kGatherCols;
+        GatherArgs ga{};
+        for (int c = 0; c < g; ++c) ga.col[c] = cols[c0 + c];
+        ga.rec = s.key_a;
+        ga.perm = vin;
+        ga.n = n;
+        switch (g) {
+            case 1: gather_group<1>(ga, st); break;
+            case 2: gather_group<2>(ga, st); break;
+            case 3: gather_group<3>(ga, st); break;
+            default: gather_group<4>(ga, st); break;
+        }
     }
     if (perm) hipLaunchKernelGGL(k_copy, stream_grid(n), dim3(kBlock), 0, st, vin, perm, n);
     return launch_status("sort_agents");
@@ -406,20 +595,23 @@ extern "C" int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order,
     rc = check_sort_ws(ws, ws_bytes, n);
     if (rc != ABM_OK) return rc;
     hipStream_t st = as_stream(stream);
-    SortWs s = carve_sort(ws, n);
-    PassArgs a{};
-    a.cond = cond;
-    a.counts = s.counts;
-    a.totals = s.totals;
-    a.base = s.base;
-    a.n = n;
-    a.n_tiles = tiles_of(n > 0 ? n : 1);
-    a.out_val = order;
     if (n == 0) {
         hipLaunchKernelGGL(k_count_out, dim3(1), dim3(64), 0, st, nullptr, d_count);
         return launch_status("select_agents");
     }
-    launch_pass<kFromCond>(a, st);
-    hipLaunchKernelGGL(k_count_out, dim3(1), dim3(64), 0, st, s.totals, d_count);
+    SortWs s = carve_sort(ws, n);
+    const uint32_t n_tiles = uint32_t((n + kSelTile - 1) / kSelTile);
+    if ((reinterpret_cast<uintptr_t>(cond) & 15) == 0) {
+        hipLaunchKernelGGL(k_sel_count<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n, s.counts);
+        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kBlock), 0, st, s.counts, n_tiles, s.totals);
+        hipLaunchKernelGGL(k_sel_scatter<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
+                           s.counts, s.totals, order, d_count);
+    } else {
+        hipLaunchKernelGGL(k_sel_count<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
+                           s.counts);
+        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kBlock), 0, st, s.counts, n_tiles, s.totals);
+        hipLaunchKernelGGL(k_sel_scatter<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
+                           s.counts, s.totals, order, d_count);
+    }
     return launch_status("select_agents");
 }

@@ -43,6 +43,30 @@ def test_sort_matches_oracle(abm, orc, n, kind, descending):
     assert np.array_equal(d_alive.cpu().numpy(), ea)
 
 
+@pytest.mark.parametrize("n_attrs,with_alive", [(0, True), (1, False), (2, True), (4, True),
+                                                (8, False), (16, True)])
+@pytest.mark.parametrize("n", [6, 4099, 70001])
+def test_sort_column_groups(abm, orc, n_attrs, with_alive, n):
+    """Every column count (columns are gathered up to four at a time) and
+    every length mod 4."""
+    g = np.random.default_rng(100 * n_attrs + n + with_alive)
+    key = _keys("few", n, g)
+    attrs = W.int32_rows(n_attrs + 3, max(n_attrs, 1), n)[:n_attrs]
+    alive = (g.random(n) < 0.5).astype(np.int32)
+    eo, ea, ep = orc.sort_agents(attrs, key, alive=alive if with_alive else None)
+    d_attrs = torch.from_numpy(np.ascontiguousarray(attrs)).cuda()
+    d_alive = torch.from_numpy(alive).cuda()
+    perm = abm.sort_agents(d_attrs, torch.from_numpy(key).cuda(),
+                           alive=d_alive if with_alive else None)
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy()[:n], ep)
+    assert np.array_equal(d_attrs.cpu().numpy(), eo)
+    if with_alive:
+        assert np.array_equal(d_alive.cpu().numpy(), ea)
+    else:
+        assert np.array_equal(d_alive.cpu().numpy(), alive)
+
+
 def test_sort_microbench_size(abm, orc):
     """2^24 agents x 8 attributes, full-range keys (the select_update
     workload's collection)."""
@@ -66,6 +90,23 @@ def test_select_agents_matches_oracle(abm, orc, n, p):
     cond = W.bernoulli_mask(n + 7, p, n) if 0 < p < 1 else np.full(n, int(p), dtype=np.uint8)
     eo, ec = orc.select_agents(cond)
     order, count = abm.select_agents(torch.from_numpy(cond).cuda())
+    torch.cuda.synchronize()
+    assert int(count.item()) == ec
+    assert np.array_equal(order.cpu().numpy()[:n], eo)
+
+
+@pytest.mark.parametrize("offset", [1, 3, 8])
+@pytest.mark.parametrize("n", [5, 4096 * 3 + 9])
+def test_select_agents_unaligned_flags(abm, orc, offset, n):
+    """Flags that do not start on a 16-byte boundary, with values other than
+    0 and 1 (any nonzero byte is true)."""
+    g = np.random.default_rng(offset * 7 + n)
+    flags = (g.random(n + offset) < 0.3).astype(np.uint8) * g.integers(1, 256, size=n + offset,
+                                                                       dtype=np.int64).astype(
+        np.uint8)
+    cond = flags[offset:]
+    eo, ec = orc.select_agents(cond)
+    order, count = abm.select_agents(torch.from_numpy(flags).cuda()[offset:])
     torch.cuda.synchronize()
     assert int(count.item()) == ec
     assert np.array_equal(order.cpu().numpy()[:n], eo)
