@@ -214,7 +214,7 @@ def sort_select_leg(abm, torch, W, n=1 << 24, reps=5):
     attrs = torch.from_numpy(W.int32_rows(8, 8, n)).to(dev)
     alive = torch.ones(n, dtype=torch.int32, device=dev)
     cond = torch.from_numpy(W.bernoulli_mask(3, 0.05, n)).to(dev)
-    ws = abm.sort_workspace(n, dev)
+    ws = abm.sort_workspace(n, dev, n_cols=9)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     order = torch.empty(n, dtype=torch.int32, device=dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)

@@ -342,22 +342,28 @@ ABM_API int abm_predation_batched_grass(const abm_batch* b, int32_t* countdown, 
  * sort_agents and select_agents (Sec. 2 API list).
  * ------------------------------------------------------------------------- */
 
-/* Workspace bytes for abm_sort_agents / abm_select_agents over n agents
- * (about 20 n bytes); 0 for n outside [0, 2^31). */
-ABM_API size_t abm_sort_workspace_bytes(int64_t n);
+/* Workspace bytes for abm_sort_agents over n agents permuting n_cols columns
+ * (the attributes, plus alive when it is non-NULL), or for abm_select_agents
+ * with n_cols = 0: 4 n for the permutation, max(12 n, n x record) where a
+ * record is n_cols int32 rounded up to a power of two, and the tile counts
+ * (about n / 4).  0 for n outside [0, 2^31) or n_cols outside [0, 17]. */
+ABM_API size_t abm_sort_workspace_bytes(int64_t n, int32_t n_cols);
 
 /* Reorder the collection by a runtime key (Sec. 2 sort_agents): afterwards
  * position j holds the agent that had the j-th smallest key (descending != 0:
  * the j-th largest); agents with equal keys keep their index order.  Every
  * attribute column and, if non-NULL, alive are permuted in place.  key: device
  * int32[capacity].  perm (device int32[capacity], may be NULL) receives the old
- * index of the agent now at each position. */
+ * index of the agent now at each position.  ws: device, 256-byte aligned, at
+ * least abm_sort_workspace_bytes(capacity, n_attrs + (alive != NULL)) bytes
+ * (else ABM_E_WORKSPACE); its contents on entry do not matter. */
 ABM_API int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t descending,
                             int32_t* perm, void* ws, size_t ws_bytes, void* stream);
 
 /* Sec. 2 select_agents: order (device int32[n]) receives the indices i with
  * cond[i] != 0 in increasing order, then the others in increasing order;
- * *d_count (device int64) the number of the former. */
+ * *d_count (device int64) the number of the former.  ws: device, 256-byte
+ * aligned, at least abm_sort_workspace_bytes(n, 0) bytes. */
 ABM_API int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order, int64_t* d_count,
                               void* ws, size_t ws_bytes, void* stream);
 

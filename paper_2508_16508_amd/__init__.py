@@ -140,11 +140,20 @@ def lib():
         L.abm_remove_agents_batched.argtypes = [i32, C.POINTER(Soa), vp, vp, vp, vp, sz, vp]
         L.abm_resolve_conflicts_batched.argtypes = [i32, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp,
                                                     vp]
+        L.abm_sort_workspace_bytes.argtypes = [i64, i32]
+        L.abm_sort_workspace_bytes.restype = sz
+        L.abm_sort_agents.argtypes = [C.POINTER(Soa), vp, i32, vp, vp, sz, vp]
+        L.abm_select_agents.argtypes = [vp, i64, vp, vp, vp, sz, vp]
+        L.abm_lob_init.argtypes = [C.POINTER(LobParams), C.POINTER(LobStatePtrs), vp]
+        L.abm_lob_step.argtypes = [C.POINTER(LobParams), C.POINTER(LobStatePtrs), i32, vp]
+        L.abm_traffic_init.argtypes = [C.POINTER(TrafficParams), C.POINTER(TrafficStatePtrs), vp]
+        L.abm_traffic_step.argtypes = [C.POINTER(TrafficParams), C.POINTER(TrafficStatePtrs), i32,
+                                       vp]
         L.abm_last_error.restype = C.c_char_p
         L.abm_version.restype = C.c_char_p
         for name in EXPORTED:
             if name not in ("abm_workspace_bytes", "abm_last_error", "abm_version",
-                            "abm_batched_workspace_bytes"):
+                            "abm_batched_workspace_bytes", "abm_sort_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -266,9 +275,12 @@ def select_indices(mask, out_idx=None, ws=None, count=None, stream=None):
     return out_idx, count
 
 
-def sort_workspace(n: int, device="cuda") -> torch.Tensor:
-    """A 256-byte-aligned workspace for sort_agents / select_agents over n agents."""
-    nbytes = int(lib().abm_sort_workspace_bytes(C.c_int64(n)))
+def sort_workspace(n: int, device="cuda", n_cols: int = 0) -> torch.Tensor:
+    """A 256-byte-aligned workspace for sort_agents over n agents permuting
+    n_cols columns (attributes plus alive), or for select_agents (n_cols 0)."""
+    nbytes = int(lib().abm_sort_workspace_bytes(n, n_cols))
+    if nbytes == 0:
+        raise ValueError(f"no sort workspace for n = {n}, n_cols = {n_cols}")
     raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-raw.data_ptr()) % 256
     return raw[off: off + nbytes]
@@ -285,7 +297,7 @@ def sort_agents(attrs, key, descending=False, alive=None, perm=None, ws=None, st
     if perm is None:
         perm = torch.empty(max(1, key.numel()), dtype=torch.int32, device=dev)
     if ws is None:
-        ws = sort_workspace(key.numel(), dev)
+        ws = sort_workspace(key.numel(), dev, dst.n_attrs + (alive is not None))
     _check(lib().abm_sort_agents(C.byref(dst), _p(key), int(bool(descending)), _p(perm), _p(ws),
                                  ws.numel(), _stream(stream)))
     return perm

@@ -3,8 +3,8 @@
 //
 // sort_agents is a least-significant-digit radix sort of (key, slot) pairs
 // with 8-bit digits, four passes over 32-bit keys, followed by a gather of
-// every attribute column through the resulting permutation (up to four
-// columns at a time, packed into one record per agent).  Each pass is
+// every attribute column through the resulting permutation (the columns
+// packed into one record per agent first).  Each pass is
 //   histogram  per 4096-key tile, 256 bins in LDS, stored digit-major;
 //   scan       one workgroup per digit scans that digit's tile counts (the
 //              tile's offset within the digit's bucket), and one workgroup
@@ -245,85 +245,136 @@ dim3 stream_grid(int64_t n) {
     return dim3(uint32_t(b < 8192 ? (b > 0 ? b : 1) : 8192));
 }
 
-// The columns go through the permutation in groups of up to kGatherCols:
-// the group is first packed into one record per agent (pack: coalesced), so
-// the gather makes one random read of a 4/8/16-byte record per agent instead
-// of one random 4-byte read per column.  Random reads, not bytes, bound a
-// gather: each costs a whole memory sector whatever its width.
-constexpr int kGatherCols = 4;
+// The columns go through the permutation packed into one record per agent:
+// a coalesced pass writes record i = (col[0][i], ..., col[C-1][i]), padded to
+// a power-of-two size (at most 128 bytes, so a record never straddles a
+// 128-byte line), and the gather makes one random record read per agent and
+// writes every column at position j.  Random reads, not bytes, bound a
+// gather: each fetches a whole line whatever its width, so one read per agent
+// replaces one per column and agent.
+constexpr int kMaxCols = ABM_MAX_ATTRS + 1;   // attributes + alive
+constexpr int kMaxRecWords = 32;
 
-template <int G> struct Rec;
-template <> struct Rec<1> { using T = int32_t; };
-template <> struct Rec<2> { using T = int2; };
-template <> struct Rec<3> { using T = int4; };
-template <> struct Rec<4> { using T = int4; };
-
-__device__ __forceinline__ int32_t field(int32_t r, int) { return r; }
-__device__ __forceinline__ int32_t field(const int2& r, int c) { return c == 0 ? r.x : r.y; }
-__device__ __forceinline__ int32_t field(const int4& r, int c) {
-    return c == 0 ? r.x : (c == 1 ? r.y : (c == 2 ? r.z : r.w));
-}
-__device__ __forceinline__ void set_field(int32_t& r, int, int32_t v) { r = v; }
-__device__ __forceinline__ void set_field(int2& r, int c, int32_t v) { (c == 0 ? r.x : r.y) = v; }
-__device__ __forceinline__ void set_field(int4& r, int c, int32_t v) {
-    (c == 0 ? r.x : (c == 1 ? r.y : (c == 2 ? r.z : r.w))) = v;
+int rec_words(int n_cols) {
+    int w = 1;
+    while (w < n_cols) w <<= 1;
+    return n_cols > 0 ? w : 0;
 }
 
 struct GatherArgs {
-    int32_t* col[kGatherCols];   // the group's columns (read by pack, written by gather)
-    void* rec;                   // n records
+    int32_t* col[kMaxRecWords];   // the columns; entries from n_cols on are unused
+    int32_t n_cols;
+    int32_t* rec;                 // n records of RW words
     const int32_t* perm;
     int64_t n;
 };
 
-// rec[i] = (col[0][i], ..., col[G-1][i])
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_pack_cols(GatherArgs g) {
-    using T = typename Rec<G>::T;
-    T* rec = static_cast<T*>(g.rec);
+// Records of 1 or 2 words: one lane per record.
+template <int RW>
+__global__ __launch_bounds__(kBlock) void k_pack_small(GatherArgs g) {
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < g.n;
          i += int64_t(gridDim.x) * kBlock) {
-        T r{};
-#pragma unroll
-        for (int c = 0; c < G; ++c) set_field(r, c, g.col[c][i]);
-        rec[i] = r;
+        if (RW == 1)
+            g.rec[i] = g.col[0][i];
+        else
+            reinterpret_cast<int2*>(g.rec)[i] = int2{g.col[0][i], g.n_cols > 1 ? g.col[1][i] : 0};
     }
 }
 
-// col[c][j] = rec[perm[j]].c.  A thread takes four consecutive j (one
-// 16-byte load of perm), so four random record reads are in flight at once.
-template <int G>
+template <int RW>
+__global__ __launch_bounds__(kBlock) void k_gather_small(GatherArgs g) {
+    for (int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x; j < g.n;
+         j += int64_t(gridDim.x) * kBlock) {
+        const int64_t p = g.perm[j];
+        if (RW == 1) {
+            g.col[0][j] = g.rec[p];
+        } else {
+            const int2 t = reinterpret_cast<const int2*>(g.rec)[p];
+            g.col[0][j] = t.x;
+            if (g.n_cols > 1) g.col[1][j] = t.y;
+        }
+    }
+}
+
+// Records of 4 to 32 words (P = RW / 4 pieces of 16 bytes), 64 records per
+// wave and round, transposed through LDS so that both sides of every global
+// access are contiguous: pack reads each column at 64 consecutive positions
+// (one lane per record) and writes the 64 records as 64 P consecutive pieces
+// (lane-consecutive); gather reads 64 / P records per load instruction (P
+// lanes per record, each record one 64-byte-aligned run) and writes each column
+// at 64 consecutive positions.  The loop runs over whole blocks, so every wave
+// meets the same barriers.
+template <int RW>
+__global__ __launch_bounds__(kBlock) void k_pack_cols(GatherArgs g) {
+    constexpr int P = RW / 4;
+    __shared__ int4 sbuf[kWaves * 64 * P];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int4* mine = sbuf + w * 64 * P;
+    int4* rec4 = reinterpret_cast<int4*>(g.rec);
+    for (int64_t b0 = int64_t(blockIdx.x) * kBlock; b0 < g.n; b0 += int64_t(gridDim.x) * kBlock) {
+        const int64_t base = b0 + w * 64;
+        const int64_t i = base + lane;
+        int32_t r[RW];
+#pragma unroll
+        for (int c = 0; c < RW; ++c) r[c] = (c < g.n_cols && i < g.n) ? g.col[c][i] : 0;
+#pragma unroll
+        for (int v = 0; v < P; ++v) mine[lane * P + v] = int4{r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]};
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int idx = k * 64 + lane;
+            if (base + idx / P < g.n) rec4[base * P + idx] = mine[idx];
+        }
+        __syncthreads();
+    }
+}
+
+template <int RW>
 __global__ __launch_bounds__(kBlock) void k_gather_recs(GatherArgs g) {
-    using T = typename Rec<G>::T;
-    const T* rec = static_cast<const T*>(g.rec);
-    const int64_t n4 = g.n >> 2;
-    const int4* perm4 = reinterpret_cast<const int4*>(g.perm);
-    for (int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x; q < n4;
-         q += int64_t(gridDim.x) * kBlock) {
-        const int4 p = perm4[q];
-        const T r0 = rec[p.x], r1 = rec[p.y], r2 = rec[p.z], r3 = rec[p.w];
+    constexpr int P = RW / 4;
+    __shared__ int4 sbuf[kWaves * 64 * P];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int4* mine = sbuf + w * 64 * P;
+    const int4* rec4 = reinterpret_cast<const int4*>(g.rec);
+    const int used = (g.n_cols + 3) / 4;   // pieces holding columns
+    for (int64_t b0 = int64_t(blockIdx.x) * kBlock; b0 < g.n; b0 += int64_t(gridDim.x) * kBlock) {
+        const int64_t base = b0 + w * 64;
 #pragma unroll
-        for (int c = 0; c < G; ++c) {
-            int32_t* out = g.col[c] + 4 * q;
-            out[0] = field(r0, c);
-            out[1] = field(r1, c);
-            out[2] = field(r2, c);
-            out[3] = field(r3, c);
+        for (int k = 0; k < P; ++k) {
+            const int idx = k * 64 + lane;
+            const int64_t j = base + idx / P;
+            const int piece = idx % P;
+            if (j < g.n && piece < used) mine[idx] = rec4[int64_t(g.perm[j]) * P + piece];
         }
+        __syncthreads();
+        const int64_t j = base + lane;
+        if (j < g.n) {
+            int32_t r[RW];
+#pragma unroll
+            for (int v = 0; v < P; ++v) {
+                const int4 t = v < used ? mine[lane * P + v] : int4{0, 0, 0, 0};
+                r[4 * v] = t.x;
+                r[4 * v + 1] = t.y;
+                r[4 * v + 2] = t.z;
+                r[4 * v + 3] = t.w;
+            }
+#pragma unroll
+            for (int c = 0; c < RW; ++c)
+                if (c < g.n_cols) g.col[c][j] = r[c];
+        }
+        __syncthreads();
     }
-    // the last n mod 4 positions
-    if (blockIdx.x == 0)
-        for (int64_t j = 4 * n4 + threadIdx.x; j < g.n; j += kBlock) {
-            const T r = rec[g.perm[j]];
-#pragma unroll
-            for (int c = 0; c < G; ++c) g.col[c][j] = field(r, c);
-        }
 }
 
-template <int G>
-void gather_group(const GatherArgs& ga, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack_cols<G>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
-    hipLaunchKernelGGL(k_gather_recs<G>, stream_grid((ga.n + 3) / 4), dim3(kBlock), 0, st, ga);
+template <int RW>
+void gather_cols(const GatherArgs& ga, hipStream_t st) {
+    if constexpr (RW <= 2) {
+        hipLaunchKernelGGL(k_pack_small<RW>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
+        hipLaunchKernelGGL(k_gather_small<RW>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
+    } else {
+        hipLaunchKernelGGL(k_pack_cols<RW>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
+        hipLaunchKernelGGL(k_gather_recs<RW>, stream_grid(ga.n), dim3(kBlock), 0, st, ga);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(const int32_t* __restrict__ src,
@@ -453,38 +504,46 @@ __global__ void k_count_out(const uint32_t* totals, int64_t* d_count) {
 }
 
 struct SortWs {
-    uint32_t *key_a, *key_b;
-    int32_t *val_a, *val_b, *stage;
+    int32_t* val_b;            // the last pass's slots: the permutation
+    uint32_t *key_a, *key_b;   // the other ping-pong buffers ...
+    int32_t* val_a;
+    int32_t* rec;              // ... whose region the records reuse afterwards
     uint32_t *counts, *totals, *base;
 };
 
 uint32_t tiles_of(int64_t n) { return uint32_t((n + kTile - 1) / kTile); }
 
-size_t sort_ws_bytes(int64_t n) {
-    const int64_t t = tiles_of(n > 0 ? n : 1);
-    const int64_t m = n > 0 ? n : 1;
-    return size_t(4 * (5 * m + int64_t(kBins) * t + 2 * kBins) + 9 * 256);
+int64_t round256(int64_t bytes) { return (bytes + 255) / 256 * 256; }
+
+// Bytes of the region shared by key_a, key_b, val_a and the records.
+int64_t region_bytes(int64_t m, int n_cols) {
+    const int64_t bufs = 3 * round256(4 * m);
+    const int64_t recs = round256(m * 4 * rec_words(n_cols));
+    return bufs > recs ? bufs : recs;
 }
 
-SortWs carve_sort(void* ws, int64_t n) {
+size_t sort_ws_bytes(int64_t n, int n_cols) {
+    const int64_t m = n > 0 ? n : 1;
+    return size_t(round256(4 * m) + region_bytes(m, n_cols) +
+                  round256(4 * int64_t(kBins) * tiles_of(m)) + 2 * round256(4 * kBins));
+}
+
+SortWs carve_sort(void* ws, int64_t n, int n_cols) {
     const int64_t m = n > 0 ? n : 1;
     char* p = static_cast<char*>(ws);
-    auto take = [&](int64_t bytes) {
-        char* q = p;
-        p += (bytes + 255) / 256 * 256;
-        return q;
-    };
     SortWs s;
-    // val_b (the final permutation) first: key_a .. stage are then one
-    // contiguous run of at least 16m bytes, which holds m 16-byte records
-    s.val_b = reinterpret_cast<int32_t*>(take(4 * m));
-    s.key_a = reinterpret_cast<uint32_t*>(take(4 * m));
-    s.key_b = reinterpret_cast<uint32_t*>(take(4 * m));
-    s.val_a = reinterpret_cast<int32_t*>(take(4 * m));
-    s.stage = reinterpret_cast<int32_t*>(take(4 * m));
-    s.counts = reinterpret_cast<uint32_t*>(take(4 * int64_t(kBins) * tiles_of(m)));
-    s.totals = reinterpret_cast<uint32_t*>(take(4 * kBins));
-    s.base = reinterpret_cast<uint32_t*>(take(4 * kBins));
+    s.val_b = reinterpret_cast<int32_t*>(p);
+    p += round256(4 * m);
+    s.key_a = reinterpret_cast<uint32_t*>(p);
+    s.key_b = reinterpret_cast<uint32_t*>(p + round256(4 * m));
+    s.val_a = reinterpret_cast<int32_t*>(p + 2 * round256(4 * m));
+    s.rec = reinterpret_cast<int32_t*>(p);
+    p += region_bytes(m, n_cols);
+    s.counts = reinterpret_cast<uint32_t*>(p);
+    p += round256(4 * int64_t(kBins) * tiles_of(m));
+    s.totals = reinterpret_cast<uint32_t*>(p);
+    p += round256(4 * kBins);
+    s.base = reinterpret_cast<uint32_t*>(p);
     return s;
 }
 
@@ -496,8 +555,8 @@ void launch_pass(const PassArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_scatter<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
 }
 
-int check_sort_ws(void* ws, size_t ws_bytes, int64_t n) {
-    const size_t need = sort_ws_bytes(n);
+int check_sort_ws(void* ws, size_t ws_bytes, int64_t n, int n_cols) {
+    const size_t need = sort_ws_bytes(n, n_cols);
     if (!ws || ws_bytes < need) {
         set_error("workspace has %zu bytes, needs %zu", ws_bytes, need);
         return ABM_E_WORKSPACE;
@@ -512,9 +571,9 @@ int check_sort_ws(void* ws, size_t ws_bytes, int64_t n) {
 
 using namespace abm;
 
-extern "C" size_t abm_sort_workspace_bytes(int64_t n) {
-    if (n < 0 || n > kMaxIndex) return 0;
-    return sort_ws_bytes(n);
+extern "C" size_t abm_sort_workspace_bytes(int64_t n, int32_t n_cols) {
+    if (n < 0 || n > kMaxIndex || n_cols < 0 || n_cols > kMaxCols) return 0;
+    return sort_ws_bytes(n, n_cols);
 }
 
 extern "C" int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t descending,
@@ -528,13 +587,19 @@ extern "C" int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t d
     if (n > 0 && !key) return fail(ABM_E_INVALID, "key is NULL");
     for (int a = 0; a < dst->n_attrs; ++a)
         if (n > 0 && !dst->attr[a]) return fail(ABM_E_INVALID, "attribute array is NULL");
+    int32_t* cols[kMaxCols];
+    int n_cols = 0;
+    for (int c = -1; c < dst->n_attrs; ++c) {
+        int32_t* col = c < 0 ? dst->alive : dst->attr[c];
+        if (col) cols[n_cols++] = col;
+    }
     int rc = check_device();
     if (rc != ABM_OK) return rc;
-    rc = check_sort_ws(ws, ws_bytes, n);
+    rc = check_sort_ws(ws, ws_bytes, n, n_cols);
     if (rc != ABM_OK) return rc;
     if (n == 0) return ABM_OK;
     hipStream_t st = as_stream(stream);
-    SortWs s = carve_sort(ws, n);
+    SortWs s = carve_sort(ws, n, n_cols);
     PassArgs a{};
     a.key = key;
     a.counts = s.counts;
@@ -559,26 +624,22 @@ extern "C" int abm_sort_agents(const abm_soa* dst, const int32_t* key, int32_t d
         vin = a.out_val;
     }
     // vin = the permutation: the agent now at position j was at vin[j].  The
-    // columns go through it in groups of up to four, packed into records in
-    // the buffers the passes no longer need (vin is val_b).
-    int32_t* cols[ABM_MAX_ATTRS + 1];
-    int n_cols = 0;
-    for (int c = -1; c < dst->n_attrs; ++c) {
-        int32_t* col = c < 0 ? dst->alive : dst->attr[c];
-        if (col) cols[n_cols++] = col;
-    }
-    for (int c0 = 0; c0 < n_cols; c0 += kGatherCols) {
-        const int g = n_cols - c0 < kGatherCols ? n_cols - c0 : kGatherCols;
+    // columns go through it packed into records, in the region of the buffers
+    // the passes no longer need (vin is val_b, outside it).
+    if (n_cols > 0) {
         GatherArgs ga{};
-        for (int c = 0; c < g; ++c) ga.col[c] = cols[c0 + c];
-        ga.rec = s.key_a;
+        for (int c = 0; c < n_cols; ++c) ga.col[c] = cols[c];
+        ga.n_cols = n_cols;
+        ga.rec = s.rec;
         ga.perm = vin;
         ga.n = n;
-        switch (g) {
-            case 1: gather_group<1>(ga, st); break;
-            case 2: gather_group<2>(ga, st); break;
-            case 3: gather_group<3>(ga, st); break;
-            default: gather_group<4>(ga, st); break;
+        switch (rec_words(n_cols)) {
+            case 1: gather_cols<1>(ga, st); break;
+            case 2: gather_cols<2>(ga, st); break;
+            case 4: gather_cols<4>(ga, st); break;
+            case 8: gather_cols<8>(ga, st); break;
+            case 16: gather_cols<16>(ga, st); break;
+            default: gather_cols<32>(ga, st); break;
         }
     }
     if (perm) hipLaunchKernelGGL(k_copy, stream_grid(n), dim3(kBlock), 0, st, vin, perm, n);
@@ -592,14 +653,14 @@ extern "C" int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order,
     if (!d_count) return fail(ABM_E_INVALID, "d_count is NULL");
     int rc = check_device();
     if (rc != ABM_OK) return rc;
-    rc = check_sort_ws(ws, ws_bytes, n);
+    rc = check_sort_ws(ws, ws_bytes, n, 0);
     if (rc != ABM_OK) return rc;
     hipStream_t st = as_stream(stream);
     if (n == 0) {
         hipLaunchKernelGGL(k_count_out, dim3(1), dim3(64), 0, st, nullptr, d_count);
         return launch_status("select_agents");
     }
-    SortWs s = carve_sort(ws, n);
+    SortWs s = carve_sort(ws, n, 0);
     const uint32_t n_tiles = uint32_t((n + kSelTile - 1) / kSelTile);
     if ((reinterpret_cast<uintptr_t>(cond) & 15) == 0) {
         hipLaunchKernelGGL(k_sel_count<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n, s.counts);

@@ -47,6 +47,22 @@ def test_workspace_bytes(abm):
     assert abm.lib().abm_version().decode().startswith("abm")
 
 
+def test_sort_workspace_bytes(abm):
+    """Permutation + max(three 4n buffers, n records of n_cols int32 rounded up
+    to a power of two) + tile counts, each part rounded up to 256 bytes."""
+    f = abm.lib().abm_sort_workspace_bytes
+    r = lambda b: (b + 255) // 256 * 256
+    n = 1 << 24
+    tiles = r(4 * 256 * (n // 4096)) + 2 * r(1024)
+    assert f(n, 0) == r(4 * n) + 3 * r(4 * n) + tiles
+    assert f(n, 2) == f(n, 0)                   # 8-byte records fit the three buffers
+    assert f(n, 3) == r(4 * n) + 16 * n + tiles  # 12 bytes -> 16-byte records
+    assert f(n, 9) == r(4 * n) + 64 * n + tiles  # 36 bytes -> 64-byte records
+    assert f(n, 17) == r(4 * n) + 128 * n + tiles
+    assert f(n, 18) == 0 and f(n, -1) == 0 and f(-1, 0) == 0 and f(1 << 31, 0) == 0
+    assert f(0, 0) == f(1, 0) > 0
+
+
 def _err(abm):
     return abm.lib().abm_last_error().decode()
 

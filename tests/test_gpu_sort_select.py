@@ -43,11 +43,11 @@ def test_sort_matches_oracle(abm, orc, n, kind, descending):
     assert np.array_equal(d_alive.cpu().numpy(), ea)
 
 
-@pytest.mark.parametrize("n_attrs,with_alive", [(0, True), (1, False), (2, True), (4, True),
-                                                (8, False), (16, True)])
+@pytest.mark.parametrize("n_attrs,with_alive", [(0, True), (1, False), (1, True), (2, True),
+                                                (4, True), (8, False), (8, True), (16, True)])
 @pytest.mark.parametrize("n", [6, 4099, 70001])
 def test_sort_column_groups(abm, orc, n_attrs, with_alive, n):
-    """Every column count (columns are gathered up to four at a time) and
+    """Every record size (1 to 17 columns: records of 1 to 32 words) and
     every length mod 4."""
     g = np.random.default_rng(100 * n_attrs + n + with_alive)
     key = _keys("few", n, g)
