@@ -97,7 +97,82 @@ def cpu_baseline(sample_seconds):
     return {"value": updates / dt, "unit": "agent-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} step(s) of seed 0: select_update + add_agents + remove_agents at "
                       f"p in {{0.001, 0.05, 0.5}}, 2^24 x 8 int32, single-threaded C oracle "
-                      f"via its ctypes wrapper ({dt:.1f} s)"}
+                      f"via its ctypes wrapper ({dt:.1f} s)",
+            "legs": cpu_baseline_legs(max(1.0, sample_seconds / 6))}
+
+
+def _timed(seconds, one):
+    """Calls one() until `seconds` have passed (at least once); (calls, total
+    of what one() returned, elapsed seconds)."""
+    calls, total, t0 = 0, 0, time.perf_counter()
+    while calls == 0 or time.perf_counter() - t0 < seconds:
+        total += one(calls)
+        calls += 1
+    return calls, total, time.perf_counter() - t0
+
+
+def cpu_baseline_legs(seconds):
+    """The oracle on bounded samples of the other legs' workloads, in the same
+    units as the GPU figures (single-threaded C oracle)."""
+    import oracle
+    from paper_2508_16508_amd import workloads as W
+    out = {}
+    for leg, multi in (("predation_large", 0), ("predation_large_multi_prey", 1)):
+        P = oracle.pred_params(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
+                               n_w0=400_000, seed=0, multi_prey=multi)
+        S = oracle.predation_init(P)
+        def one(_):
+            st = oracle.predation_step(P, S)
+            return st["live_s"] + st["live_w"]
+        n, upd, dt = _timed(seconds, one)
+        out[leg] = {"value": upd / dt, "unit": "agent-updates/s",
+                    "sample": f"steps 0-{n - 1} of the 2048x2048 model ({dt:.1f} s)"}
+    specs = W.batched_models(0, 4096)
+    by_size = sorted(range(len(specs)), key=lambda m: specs[m].side)
+    pick = by_size[:: len(specs) // 32][:32]
+    def one(k):
+        sp = specs[pick[k % len(pick)]]
+        P = oracle.pred_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s, cap_w=sp.cap_w,
+                               n_s0=sp.n_s0, n_w0=sp.n_w0)
+        S = oracle.predation_init(P)
+        return sum(st["live_s"] + st["live_w"] for st in oracle.predation_run(P, S, 20))
+    n, upd, dt = _timed(seconds, one)
+    out["batched"] = {"value": upd / dt, "unit": "agent-updates/s",
+                      "sample": f"{n} model run(s) of 20 steps, cycling over the 32 plain-path "
+                                f"sample models (every 128th by size) ({dt:.1f} s, init included)"}
+    def one(r):
+        P = oracle.traffic_params(100, seed=1 + r)
+        S = oracle.traffic_init(P)
+        oracle.traffic_run(P, S, 10)
+        return sum(st["cars"] for st in oracle.traffic_run(P, S, 1000))
+    n, cars, dt = _timed(seconds, one)
+    out["traffic"] = {"value": cars / dt, "unit": "car-updates/s",
+                      "sample": f"roads 0-{n - 1}, 10 + 1000 steps each ({dt:.1f} s, warm-up "
+                                "steps included in the time, not in the count)"}
+    def one(b):
+        P = oracle.lob_params(cap=1000, traders=100, seed=1 + b)
+        S = oracle.lob_init(P)
+        oracle.lob_run(P, S, 20)
+        oracle.lob_run(P, S, 100)
+        return 100
+    n, steps, dt = _timed(seconds, one)
+    out["lob"] = {"value": steps / dt, "unit": "book-steps/s",
+                  "sample": f"books 0-{n - 1}, 20 + 100 steps each ({dt:.1f} s, warm-up steps "
+                            "included in the time, not in the count)"}
+    m = 1 << 22
+    g = np.random.default_rng(7)
+    key = g.integers(-2 ** 31, 2 ** 31, size=m, dtype=np.int64).astype(np.int32)
+    attrs = W.int32_rows(8, 8, m)
+    alive = np.ones(m, dtype=np.int32)
+    n, agents, dt = _timed(seconds, lambda _: (oracle.sort_agents(attrs, key, alive=alive), m)[1])
+    out["sort_agents"] = {"value": agents / dt, "unit": "agents/s",
+                          "sample": f"{n} sort(s) of 2^22 agents x 8 int32 + alive, full-range "
+                                    f"keys ({dt:.1f} s)"}
+    cond = W.bernoulli_mask(3, 0.05, 1 << 24)
+    n, agents, dt = _timed(seconds, lambda _: (oracle.select_agents(cond), 1 << 24)[1])
+    out["select_agents"] = {"value": agents / dt, "unit": "agents/s",
+                            "sample": f"{n} call(s) on 2^24 Bernoulli(0.05) flags ({dt:.1f} s)"}
+    return out
 
 
 def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps=20):
