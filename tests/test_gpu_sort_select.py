@@ -120,3 +120,12 @@ def test_sort_rejects_small_workspace_and_bad_counts(abm):
         abm.sort_agents(attrs, key, ws=small)
     with pytest.raises(abm.AbmError):
         abm.select_agents(torch.zeros(5000, dtype=torch.uint8, device="cuda"), ws=small)
+    # enough for select_agents and for 2 columns, not for the records of 9
+    ws0 = abm.sort_workspace(5000, n_cols=0)
+    abm.select_agents(torch.zeros(5000, dtype=torch.uint8, device="cuda"), ws=ws0)
+    abm.sort_agents(torch.zeros((2, 5000), dtype=torch.int32, device="cuda"), key, ws=ws0)
+    with pytest.raises(abm.AbmError):
+        abm.sort_agents(torch.zeros((8, 5000), dtype=torch.int32, device="cuda"), key,
+                        alive=torch.zeros(5000, dtype=torch.int32, device="cuda"), ws=ws0)
+    with pytest.raises(ValueError):
+        abm.sort_workspace(5000, n_cols=18)
