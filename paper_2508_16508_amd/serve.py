@@ -133,7 +133,7 @@ class Scheduler:
     callable returning seconds since the start of the trace."""
 
     def __init__(self, runner, cell_capacity, sheep_capacity, wolf_capacity, max_active=4096,
-                 slot_step_budget=1 << 22, clock=None, sleep=None, log=None, log_every_s=5.0):
+                 slot_step_budget=1 << 23, clock=None, sleep=None, log=None, log_every_s=5.0):
         self.runner = runner
         self.cells = RangeAllocator(cell_capacity)
         self.sheep = RangeAllocator(sheep_capacity)
