@@ -112,6 +112,17 @@ def test_select_agents_unaligned_flags(abm, orc, offset, n):
     assert np.array_equal(order.cpu().numpy()[:n], eo)
 
 
+def test_empty_collection(abm, orc):
+    """n = 0: nothing to sort, the count is 0."""
+    attrs = torch.zeros((3, 0), dtype=torch.int32, device="cuda")
+    perm = abm.sort_agents(attrs, torch.zeros(0, dtype=torch.int32, device="cuda"),
+                           alive=torch.zeros(0, dtype=torch.int32, device="cuda"))
+    order, count = abm.select_agents(torch.zeros(0, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0 and perm.numel() >= 0 and order.numel() >= 0
+    assert orc.select_agents(np.zeros(0, dtype=np.uint8))[1] == 0
+
+
 def test_sort_rejects_small_workspace_and_bad_counts(abm):
     key = torch.zeros(5000, dtype=torch.int32, device="cuda")
     attrs = torch.zeros((1, 5000), dtype=torch.int32, device="cuda")
