@@ -442,18 +442,44 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(const uint8_t* __restrict_
 }
 
 // counts[t] = the set flags before tile t (exclusive scan); totals[0] = all.
-// One workgroup.
-__global__ __launch_bounds__(kBlock) void k_sel_scan(uint32_t* counts, uint32_t n_tiles,
-                                                     uint32_t* totals) {
+// One workgroup of 1024 threads, four consecutive counts per thread (one
+// round for up to 4096 tiles, i.e. 2^24 flags).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_sel_scan(uint32_t* counts, uint32_t n_tiles,
+                                                           uint32_t* totals) {
+    __shared__ uint32_t wtot[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < n_tiles; c0 += kBlock) {
-        const uint32_t i = c0 + threadIdx.x;
-        const uint32_t v = i < n_tiles ? counts[i] : 0u;
-        uint32_t all;
-        const uint32_t ex = block_excl_scan(v, &all);
-        if (i < n_tiles) counts[i] = carry + ex;
+    for (uint32_t c0 = 0; c0 < n_tiles; c0 += 4 * kScanThreads) {
+        const uint32_t i = c0 + 4 * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = i + q < n_tiles ? counts[i + q] : 0u;
+        const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+        uint32_t x = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wtot[w] = x;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int q = 0; q < kScanThreads / 64; ++q) {
+            before += q < w ? wtot[q] : 0u;
+            all += wtot[q];
+        }
+        uint32_t ex = carry + before + x - mine;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i + q < n_tiles) {
+                counts[i + q] = ex;
+                ex += v[q];
+            }
         carry += all;
-        __syncthreads();   // wtot is reused by the next chunk
+        __syncthreads();   // wtot is reused by the next round
     }
     if (threadIdx.x == 0) totals[0] = carry;
 }
@@ -664,13 +690,15 @@ extern "C" int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order,
     const uint32_t n_tiles = uint32_t((n + kSelTile - 1) / kSelTile);
     if ((reinterpret_cast<uintptr_t>(cond) & 15) == 0) {
         hipLaunchKernelGGL(k_sel_count<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n, s.counts);
-        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kBlock), 0, st, s.counts, n_tiles, s.totals);
+        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
+                           s.totals);
         hipLaunchKernelGGL(k_sel_scatter<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts, s.totals, order, d_count);
     } else {
         hipLaunchKernelGGL(k_sel_count<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts);
-        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kBlock), 0, st, s.counts, n_tiles, s.totals);
+        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
+                           s.totals);
         hipLaunchKernelGGL(k_sel_scatter<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts, s.totals, order, d_count);
     }

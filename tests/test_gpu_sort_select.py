@@ -84,7 +84,7 @@ def test_sort_microbench_size(abm, orc):
     assert np.array_equal(got[:, sample], attrs[:, ep[sample]])
 
 
-@pytest.mark.parametrize("n", [1, 64, 4097, 1 << 16, 1 << 24])
+@pytest.mark.parametrize("n", [1, 64, 4097, 1 << 16, 1 << 24, (1 << 24) + 12345])
 @pytest.mark.parametrize("p", [0.0, 0.001, 0.5, 1.0])
 def test_select_agents_matches_oracle(abm, orc, n, p):
     cond = W.bernoulli_mask(n + 7, p, n) if 0 < p < 1 else np.full(n, int(p), dtype=np.uint8)
