@@ -216,6 +216,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
         if (threadIdx.x < kBins) dstart[threadIdx.x] = before + x - dtot;
     }
     __syncthreads();
+    // where each digit's run of this tile goes, less its start in the tile
+    // (read from global memory once per digit, not once per key)
+    __shared__ int64_t goff[kBins];
+    if (threadIdx.x < kBins) {
+        const int d = threadIdx.x;
+        goff[d] = int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] - int64_t(dstart[d]);
+    }
     // stage the tile in digit order
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
@@ -232,9 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PassArgs a) {
     const int32_t n_tile = left < kTile ? int32_t(left) : int32_t(kTile);
     for (int32_t p = threadIdx.x; p < n_tile; p += kBlock) {
         const uint32_t kk = skey[p];
-        const uint32_t d = (kk >> a.shift) & 0xFFu;
-        const int64_t dst = int64_t(a.base[d]) + a.counts[int64_t(d) * a.n_tiles + t] +
-                            (p - int32_t(dstart[d]));
+        const int64_t dst = goff[(kk >> a.shift) & 0xFFu] + p;
         a.out_key[dst] = kk;
         a.out_val[dst] = sval[p];
     }
