@@ -99,35 +99,49 @@ __global__ __launch_bounds__(kBlock) void k_hist(PassArgs a) {
     for (int d = threadIdx.x; d < kBins; d += kBlock) a.counts[int64_t(d) * a.n_tiles + t] = hist[d];
 }
 
-// One workgroup per digit: exclusive scan of the digit's tile counts in place;
-// the digit's total to totals[d].
-__global__ __launch_bounds__(kBlock) void k_digit_scan(PassArgs a) {
-    __shared__ uint32_t lds[kWaves + 1];
-    uint32_t* row = a.counts + int64_t(blockIdx.x) * a.n_tiles;
+// Exclusive scan in place of row r = blockIdx.x of n_tiles counts (the tile
+// counts of one radix digit, or of the set flags); totals[r] = the row's sum.
+// One workgroup of 1024 threads per row, four consecutive counts per thread
+// (one round for up to 4096 tiles, i.e. 2^24 keys).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_rows(uint32_t* rows, uint32_t n_tiles,
+                                                            uint32_t* totals) {
+    uint32_t* counts = rows + int64_t(blockIdx.x) * n_tiles;
+    __shared__ uint32_t wtot[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < a.n_tiles; c0 += kBlock) {
-        const uint32_t i = c0 + threadIdx.x;
-        const uint32_t v = i < a.n_tiles ? row[i] : 0u;
-        // inclusive scan within the wave
-        uint32_t x = v;
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (uint32_t c0 = 0; c0 < n_tiles; c0 += 4 * kScanThreads) {
+        const uint32_t i = c0 + 4 * threadIdx.x;
+        uint32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = i + q < n_tiles ? counts[i + q] : 0u;
+        const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+        uint32_t x = mine;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
+        if (lane == 63) wtot[w] = x;
         __syncthreads();
-        if (lane == 63) lds[w] = x;
-        __syncthreads();
-        uint32_t before = carry, all = carry;
-        for (int q = 0; q < kWaves; ++q) {
-            before += q < w ? lds[q] : 0u;
-            all += lds[q];
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int q = 0; q < kScanThreads / 64; ++q) {
+            before += q < w ? wtot[q] : 0u;
+            all += wtot[q];
         }
-        if (i < a.n_tiles) row[i] = before + x - v;
-        carry = all;
+        uint32_t ex = carry + before + x - mine;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i + q < n_tiles) {
+                counts[i + q] = ex;
+                ex += v[q];
+            }
+        carry += all;
+        __syncthreads();   // wtot is reused by the next round
     }
-    if (threadIdx.x == 0) a.totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kBins) void k_digit_base(PassArgs a) {
@@ -446,49 +460,6 @@ __global__ __launch_bounds__(kBlock) void k_sel_count(const uint8_t* __restrict_
     if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
-// counts[t] = the set flags before tile t (exclusive scan); totals[0] = all.
-// One workgroup of 1024 threads, four consecutive counts per thread (one
-// round for up to 4096 tiles, i.e. 2^24 flags).
-constexpr int kScanThreads = 1024;
-
-__global__ __launch_bounds__(kScanThreads) void k_sel_scan(uint32_t* counts, uint32_t n_tiles,
-                                                           uint32_t* totals) {
-    __shared__ uint32_t wtot[kScanThreads / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < n_tiles; c0 += 4 * kScanThreads) {
-        const uint32_t i = c0 + 4 * threadIdx.x;
-        uint32_t v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = i + q < n_tiles ? counts[i + q] : 0u;
-        const uint32_t mine = v[0] + v[1] + v[2] + v[3];
-        uint32_t x = mine;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wtot[w] = x;
-        __syncthreads();
-        uint32_t before = 0, all = 0;
-#pragma unroll
-        for (int q = 0; q < kScanThreads / 64; ++q) {
-            before += q < w ? wtot[q] : 0u;
-            all += wtot[q];
-        }
-        uint32_t ex = carry + before + x - mine;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (i + q < n_tiles) {
-                counts[i + q] = ex;
-                ex += v[q];
-            }
-        carry += all;
-        __syncthreads();   // wtot is reused by the next round
-    }
-    if (threadIdx.x == 0) totals[0] = carry;
-}
-
 // The tile's set flags go to [counts[t], ...) and its clear flags to
 // [total + (t * 4096 - counts[t]), ...), both in index order; the tile is
 // staged in LDS in that order so that consecutive threads write consecutive
@@ -581,7 +552,8 @@ SortWs carve_sort(void* ws, int64_t n, int n_cols) {
 template <int SRC>
 void launch_pass(const PassArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_hist<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_digit_scan, dim3(kBins), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_scan_rows, dim3(kBins), dim3(kScanThreads), 0, st, a.counts, a.n_tiles,
+                       a.totals);
     hipLaunchKernelGGL(k_digit_base, dim3(1), dim3(kBins), 0, st, a);
     hipLaunchKernelGGL(k_scatter<SRC>, dim3(a.n_tiles), dim3(kBlock), 0, st, a);
 }
@@ -695,14 +667,14 @@ extern "C" int abm_select_agents(const uint8_t* cond, int64_t n, int32_t* order,
     const uint32_t n_tiles = uint32_t((n + kSelTile - 1) / kSelTile);
     if ((reinterpret_cast<uintptr_t>(cond) & 15) == 0) {
         hipLaunchKernelGGL(k_sel_count<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n, s.counts);
-        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
+        hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
                            s.totals);
         hipLaunchKernelGGL(k_sel_scatter<true>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts, s.totals, order, d_count);
     } else {
         hipLaunchKernelGGL(k_sel_count<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts);
-        hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
+        hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(kScanThreads), 0, st, s.counts, n_tiles,
                            s.totals);
         hipLaunchKernelGGL(k_sel_scatter<false>, dim3(n_tiles), dim3(kBlock), 0, st, cond, n,
                            s.counts, s.totals, order, d_count);
