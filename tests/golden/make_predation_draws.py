@@ -3,7 +3,9 @@
 The expected states in ``predation_hand_1x1.txt`` and ``predation_hand_3x3.txt``
 were worked out by hand from these draws and the model rules (Sec. 5.1, with
 the step order move, eat, breed, die, regrow); ``predation_multi_prey_1x1.txt``
-from the prey and eat keys of one step.  This script calls only the oracle's
+from the prey and eat keys of one step; ``predation_moves_8dirs.txt`` from the
+move draws of step 0 for seed 30, whose eight sheep draw all eight directions.
+This script calls only the oracle's
 RNG (which is itself pinned to the published SplitMix64 vectors).
 
     python tests/golden/make_predation_draws.py
@@ -53,7 +55,16 @@ def dump_keys(seed, step, n_s, n_w):
         print(f"t={step} wolf {j} W_EAT_KEY = {O.rng(seed, step, j, 0x24)}")
 
 
+def dump_moves(seed, step, n_s, n_w):
+    print(f"# seed={seed} step={step}")
+    for sp, n, p in (("sheep", n_s, 0x13), ("wolf", n_w, 0x23)):
+        for i in range(n):
+            h = O.rng(seed, step, i, p)
+            print(f"t={step} {sp} {i} {NAMES[p]} = {h} dir={h >> 29}")
+
+
 if __name__ == "__main__":
     dump(5, 1, 4, 2, 2)
     dump(11, 9, 3, 3, 2)
     dump_keys(21, 7, 4, 3)
+    dump_moves(30, 0, 8, 8)

@@ -389,3 +389,34 @@ def test_multi_prey_worked_cell(orc):
         assert ns == min(n_s, 3), case
         assert list(S.sheep["alive"]) == exp[f"{case}.sheep_alive_after"], case
         assert list(S.wolves["e"]) == exp[f"{case}.wolf_e_after"], case
+
+
+def test_move_every_direction_worked_by_hand(orc):
+    """Every one of the eight move directions (Sec. 5.1, Fig. 2), each with its
+    exact displacement, including wraps in x, in y and in both, on a 5x5
+    torus worked by hand (tests/golden/predation_moves_8dirs.txt).  Swapping
+    any two entries of the direction table, or dropping the wrap, fails here."""
+    meta, exp = _load_hand("predation_moves_8dirs.txt")
+    P = orc.pred_params(**meta)
+    S = orc._empty_state(P)
+    for sp in SPECIES:
+        for f in FIELDS:
+            getattr(S, sp)[f][:] = exp[f"before.{sp}.{f}"]
+    S.step = 0
+    # the draws of the fixture are the oracle's draws for this seed and step
+    for sp, purpose in (("sheep", 0x13), ("wolves", 0x23)):
+        dirs = [orc.rng(P.seed, 0, i, purpose) >> 29 for i in range(8)]
+        assert dirs == exp[f"draws.{sp}"], sp
+    assert sorted(exp["draws.sheep"]) == list(range(8))
+    orc.pred_move(P, S)
+    for sp in SPECIES:
+        for f in FIELDS:
+            assert list(getattr(S, sp)[f]) == exp[f"after.{sp}.{f}"], f"{sp}.{f}"
+    # each live agent's displacement is the table entry of its draw
+    for sp in SPECIES:
+        live = np.flatnonzero(np.array(exp[f"before.{sp}.alive"]))
+        for i in live:
+            d = exp[f"draws.{sp}"][i]
+            dx = (exp[f"after.{sp}.x"][i] - exp[f"before.{sp}.x"][i]) % P.W
+            dy = (exp[f"after.{sp}.y"][i] - exp[f"before.{sp}.y"][i]) % P.H
+            assert dx == exp["dirs.dx"][d] % P.W and dy == exp["dirs.dy"][d] % P.H, (sp, i, d)
