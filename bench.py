@@ -218,6 +218,7 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     d1 = batch.descriptors()
     assert all(d.step == steps for d in d1)
     updates = sum(d.updates for d in d1) - u0
+    err = abm.workspace_error(batch.ws)
     cells = sum(sp.side * sp.side for sp in specs)
     del batch, graph
     torch.cuda.empty_cache()
@@ -250,6 +251,7 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
             "plain_sample": f"{len(pick)} models (every {len(specs) // plain_models}th by size), "
                             f"{plain_steps} steps each, one-model multi-launch path",
             "batched_over_plain": rate_b / rate_p,
+            "workspace_error": err,
             "tuning": {"block_threads": tuning["block_threads"], "items": tuning["items"],
                        "candidates_ms_per_4_steps": tuning["timings_ms"]}}
 
@@ -386,6 +388,7 @@ def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18):
                       log=lambda m: print("served:", m, file=sys.stderr, flush=True))
     rep = sch.serve(reqs)
     out = rep.summary()
+    out["workspace_error"] = runner.workspace_error
     out["workload"] = (f"Poisson arrivals at {rate:g}/s for {seconds:g} s ({len(reqs)} requests), "
                        "side log-uniform [32, 1024], steps log-uniform [100, 5000], "
                        "sheep = cells/10, wolves = cells/40, capacities 4x")
@@ -483,6 +486,10 @@ def main():
     ms_total = g0.elapsed_time(g1)
     ms_per_step = ms_total / args.steps
 
+    # the kernels' give-up word: set if a bounded wait of the single-pass scan
+    # ever expired (its ordering assumption failed), which would make the
+    # timed state wrong
+    micro_err = abm.workspace_error(ws)
     # correctness of the timed work: the last density's counts and restored alive
     last = sets[(args.warmup + args.steps - 1) % len(sets)][-1]
     c = cnt.cpu().numpy()
@@ -530,6 +537,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "kernel_sources": src_hash,
+        "workspace_error": {"microbench": micro_err},
     }
     del sets, dst
     torch.cuda.empty_cache()
@@ -558,7 +566,16 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    for leg in ("predation_small", "predation_large", "predation_large_multi_prey", "batched",
+                "served"):
+        if leg in out:
+            out["workspace_error"][leg] = out[leg]["workspace_error"]
     print(json.dumps(out), flush=True)
+    bad = {k: v for k, v in out["workspace_error"].items() if v}
+    if bad:
+        print(f"bench.py: a kernel's bounded wait gave up in {sorted(bad)}: the timed state is "
+              "not valid", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

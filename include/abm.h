@@ -155,7 +155,8 @@ ABM_API int abm_remove_agents(const abm_soa* dst, const uint8_t* kill_mask, int6
  *   active    device uint8[n_claims] or NULL;
  *   best      device uint64[n_targets] (overwritten; no reset needed);
  *   winner    device int32[n_targets]; won device uint8[n_claims].
- * n_claims < 2^32.  No workspace.
+ * 0 <= n_claims < 2^31 (claim indices fit winner[]'s int32), else
+ * ABM_E_INVALID before any launch.  No workspace.
  * ------------------------------------------------------------------------- */
 ABM_API int abm_resolve_conflicts(int64_t n_claims, const int32_t* target, const uint32_t* prio,
                           const uint8_t* active, int64_t n_targets, uint64_t* best,

@@ -71,8 +71,9 @@ using namespace abm;
 extern "C" int abm_resolve_conflicts(int64_t n_claims, const int32_t* target, const uint32_t* prio,
                                      const uint8_t* active, int64_t n_targets, uint64_t* best,
                                      int32_t* winner, uint8_t* won, void* stream) {
-    if (n_claims < 0 || n_claims > int64_t(0xFFFFFFFFll))
-        return fail(ABM_E_INVALID, "n_claims must be in [0, 2^32)");
+    // winner[] holds claim indices as int32, with -1 for "no claim"
+    if (n_claims < 0 || n_claims > kMaxIndex)
+        return fail(ABM_E_INVALID, "n_claims must be in [0, 2^31)");
     if (n_targets < 0 || n_targets > kMaxIndex)
         return fail(ABM_E_INVALID, "n_targets must be in [0, 2^31)");
     if (n_claims > 0 && (!target || !prio || !won))

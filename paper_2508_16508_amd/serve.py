@@ -269,6 +269,7 @@ class GpuRunner:
         self.keep_results = keep_results
         self.results = {}
         self.device = device
+        self.workspace_error = 0
 
     def _team_model(self, r) -> bool:
         return self.team_size > 1 and r.req.cells + r.req.cap_s + r.req.cap_w >= self.team_min_size
@@ -322,6 +323,12 @@ class GpuRunner:
                                                        self.ws.numel(), abm._stream()))
         raw = self.desc[: n * self.desc_size].cpu().numpy().tobytes()   # synchronises
         out = (abm.ModelDesc * n).from_buffer_copy(raw)
+        # the error word is sticky: non-zero once any team barrier or bounded
+        # wait of this workspace has given up, which leaves the states invalid
+        self.workspace_error = abm.workspace_error(self.ws)
+        if self.workspace_error:
+            raise RuntimeError("batched kernel: a team barrier gave up (workspace error word "
+                               "set); the served states are not valid")
         return [(d.step, d.updates) for d in out]
 
     def finish(self, r: Running):

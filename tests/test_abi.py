@@ -105,6 +105,10 @@ def test_invalid_arguments_rejected_on_host(abm):
         abm.ABM_E_INVALID
     assert L.abm_resolve_conflicts(4, None, None, None, 4, None, None, None, None) == \
         abm.ABM_E_INVALID
+    # resolve: claim indices must fit winner[]'s int32 (2^31 claims is one too many)
+    p = C.c_void_p(256)
+    assert L.abm_resolve_conflicts(1 << 31, p, p, None, 4, p, p, p, None) == abm.ABM_E_INVALID
+    assert "2^31" in _err(abm)
     # select_indices: missing count
     assert L.abm_select_indices(None, 0, None, None, None, 0, None) == abm.ABM_E_INVALID
     # workspace init with nothing

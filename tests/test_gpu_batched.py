@@ -229,9 +229,9 @@ def test_team_launch_rejects_bad_tuning(abm):
 @pytest.mark.parametrize("team_size", [1, 2])
 def test_resume_from_an_edited_state(abm, orc, team_size):
     """Between launches, agents are killed in low slots and placed in the
-    highest slots: the next launch finds every live agent (it derives the
-    high-water mark of each species from the state) and matches the oracle run
-    from the edited state."""
+    highest slots: the next launch scans every slot of each species, finds
+    every live agent wherever it sits, and matches the oracle run from the
+    edited state."""
     kws = [dict(W=48, H=40, seed=3, cap_s=3000, cap_w=900, n_s0=300, n_w0=80),
            dict(W=30, H=30, seed=9, cap_s=1000, cap_w=400, n_s0=100, n_w0=30)]
     batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 40,
