@@ -77,101 +77,175 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(sample_seconds):
-    """The oracle as it stands, single-threaded, on seed 0's inputs."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _med(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def cpu_baseline(seeds=3, reps=5):
+    """The oracle as it stands -- plain single-threaded C, built here with
+    -O3 -march=native -- pinned to one core of this host.  Each call is timed
+    alone (perf_counter around one C call on preallocated arrays: no input
+    generation, no copies in the timed region); the median of `reps` calls
+    per (seed, density, op).  The main figure is the microbenchmark step
+    (select_update + add_agents + remove_agents at the three densities) on
+    seeds 0..seeds-1, in agent updates per second like `value`."""
+    import tempfile
     import oracle
+    from oracle import build as obuild
     from paper_2508_16508_amd import workloads as W
-    cases = [W.select_update_case(0, p) for p in W.DENSITIES]
-    reps, updates, t0 = 0, 0, time.perf_counter()
-    while True:
-        for c in cases:
-            alive = (1 - c.mask).astype(np.int32)
-            out, applied, _ = oracle.select_update(c.attrs, c.mask, c.records)
-            out, al, added, _ = oracle.add_agents(out, alive, c.records)
-            al, removed = oracle.remove_agents(al, c.mask)
-            updates += applied + added + removed
-        reps += 1
-        if time.perf_counter() - t0 >= sample_seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "agent-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} step(s) of seed 0: select_update + add_agents + remove_agents at "
-                      f"p in {{0.001, 0.05, 0.5}}, 2^24 x 8 int32, single-threaded C oracle "
-                      f"via its ctypes wrapper ({dt:.1f} s)",
-            "legs": cpu_baseline_legs(max(1.0, sample_seconds / 6))}
+    allowed = sorted(os.sched_getaffinity(0))
+    info = {"cores": 1, "core_id": allowed[0], "nproc": len(allowed),
+            "cpu_count": os.cpu_count(), "cpu_model": _cpu_model(),
+            "build": "gcc -O3 -march=native (oracle/abm_oracle.c, built on this host)"}
+    oracle.use_library(obuild.build_native(tempfile.mkdtemp(prefix="abm_oracle_")))
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
+        t_total, updates = 0.0, 0
+        for seed in range(seeds):
+            for p in W.DENSITIES:
+                c = W.select_update_case(seed, p)
+                out = c.attrs.copy()
+                free = (1 - c.mask).astype(np.int32)
+                ts = {"select": [], "add": [], "remove": []}
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    a, _ = oracle.select_update_into(out, c.mask, c.records)
+                    ts["select"].append(time.perf_counter() - t0)
+                    alive = free.copy()
+                    t0 = time.perf_counter()
+                    n_add, _ = oracle.add_agents_into(out, alive, c.records)
+                    ts["add"].append(time.perf_counter() - t0)
+                    t0 = time.perf_counter()
+                    n_rem = oracle.remove_agents_into(alive, c.mask)
+                    ts["remove"].append(time.perf_counter() - t0)
+                assert a == n_add == n_rem == c.k
+                t_total += sum(_med(v) for v in ts.values())
+                updates += 3 * c.k
+                del c, out, free, alive
+        legs = cpu_baseline_legs(oracle, W)
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    out = {"value": updates / t_total, "unit": "agent-updates/s", "kind": "oracle",
+           "sample": f"seeds 0-{seeds - 1} of the 2^24 x 8 microbenchmark: select_update + "
+                     f"add_agents + remove_agents at p in {{0.001, 0.05, 0.5}}, median of {reps} "
+                     f"calls each ({t_total:.2f} s of oracle time per pass)",
+           "legs": legs}
+    out.update(info)
+    return out
 
 
-def _timed(seconds, one):
-    """Calls one() until `seconds` have passed (at least once); (calls, total
-    of what one() returned, elapsed seconds)."""
-    calls, total, t0 = 0, 0, time.perf_counter()
-    while calls == 0 or time.perf_counter() - t0 < seconds:
-        total += one(calls)
-        calls += 1
-    return calls, total, time.perf_counter() - t0
-
-
-def cpu_baseline_legs(seconds):
-    """The oracle on bounded samples of the other legs' workloads, in the same
-    units as the GPU figures (single-threaded C oracle)."""
-    import oracle
-    from paper_2508_16508_amd import workloads as W
-    out = {}
-    for leg, multi in (("predation_large", 0), ("predation_large_multi_prey", 1)):
-        P = oracle.pred_params(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
-                               n_w0=400_000, seed=0, multi_prey=multi)
+def _pred_leg(oracle, kw, steps, runs=1):
+    """agent updates/s of the oracle on one predation model: `steps` steps
+    from the initial state (init not timed), median over `runs` seeds."""
+    rates = []
+    for r in range(runs):
+        P = oracle.pred_params(**dict(kw, seed=kw.get("seed", 0) + r))
         S = oracle.predation_init(P)
-        def one(_):
-            st = oracle.predation_step(P, S)
-            return st["live_s"] + st["live_w"]
-        n, upd, dt = _timed(seconds, one)
-        out[leg] = {"value": upd / dt, "unit": "agent-updates/s",
-                    "sample": f"steps 0-{n - 1} of the 2048x2048 model ({dt:.1f} s)"}
+        t0 = time.perf_counter()
+        st = oracle.predation_run(P, S, steps)
+        dt = time.perf_counter() - t0
+        rates.append(sum(s["live_s"] + s["live_w"] for s in st) / dt)
+    return _med(rates)
+
+
+def cpu_baseline_legs(oracle, W):
+    """The pinned oracle on bounded samples of the other legs' workloads, in
+    the same units as the GPU figures."""
+    out = {}
+    out["predation_small"] = {
+        "value": _pred_leg(oracle, dict(seed=0), 200, runs=3), "unit": "agent-updates/s",
+        "sample": "the 64x64 model (400 / 100 agents), 200 steps, seeds 0-2, median"}
+    big = dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000, n_w0=400_000,
+               seed=0)
+    out["predation_large"] = {"value": _pred_leg(oracle, big, 10), "unit": "agent-updates/s",
+                              "sample": "steps 0-9 of the 2048x2048 model, seed 0"}
+    out["predation_large_multi_prey"] = {
+        "value": _pred_leg(oracle, dict(big, multi_prey=1), 10), "unit": "agent-updates/s",
+        "sample": "steps 0-9 of the 2048x2048 model with multi-prey, seed 0"}
     specs = W.batched_models(0, 4096)
     by_size = sorted(range(len(specs)), key=lambda m: specs[m].side)
-    pick = by_size[:: len(specs) // 32][:32]
-    def one(k):
-        sp = specs[pick[k % len(pick)]]
-        P = oracle.pred_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s, cap_w=sp.cap_w,
-                               n_s0=sp.n_s0, n_w0=sp.n_w0)
+    upd, dt = 0, 0.0
+    for m in by_size[:: len(specs) // 32][:32]:
+        sp = specs[m]
+        P = oracle.pred_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s,
+                               cap_w=sp.cap_w, n_s0=sp.n_s0, n_w0=sp.n_w0)
         S = oracle.predation_init(P)
-        return sum(st["live_s"] + st["live_w"] for st in oracle.predation_run(P, S, 20))
-    n, upd, dt = _timed(seconds, one)
+        t0 = time.perf_counter()
+        upd += sum(s["live_s"] + s["live_w"] for s in oracle.predation_run(P, S, 20))
+        dt += time.perf_counter() - t0
     out["batched"] = {"value": upd / dt, "unit": "agent-updates/s",
-                      "sample": f"{n} model run(s) of 20 steps, cycling over the 32 plain-path "
-                                f"sample models (every 128th by size) ({dt:.1f} s, init included)"}
-    def one(r):
+                      "sample": "32 models of the 4096-model batch (every 128th by size), "
+                                "20 steps each, init not timed"}
+    trace = W.served_trace(0)
+    by_side = sorted(range(len(trace)), key=lambda i: trace[i].side)
+    upd, dt = 0, 0.0
+    for i in by_side[:: len(trace) // 24][:24]:
+        q = trace[i]
+        cells = q.side * q.side
+        P = oracle.pred_params(W=q.side, H=q.side, seed=q.seed & 0xFFFFFFFF,
+                               cap_s=max(1, 4 * (cells // 10)), cap_w=max(1, 4 * (cells // 40)),
+                               n_s0=cells // 10, n_w0=cells // 40)
+        S = oracle.predation_init(P)
+        t0 = time.perf_counter()
+        upd += sum(s["live_s"] + s["live_w"] for s in oracle.predation_run(P, S,
+                                                                          min(q.steps, 20)))
+        dt += time.perf_counter() - t0
+    out["served"] = {"value": upd / dt, "unit": "agent-updates/s",
+                     "sample": "24 requests of the served trace spread over its sides (every "
+                               f"{len(trace) // 24}th by side), their first min(steps, 20) "
+                               "steps each, init not timed"}
+    upd, dt = 0, 0.0
+    for r in range(3):
         P = oracle.traffic_params(100, seed=1 + r)
         S = oracle.traffic_init(P)
         oracle.traffic_run(P, S, 10)
-        return sum(st["cars"] for st in oracle.traffic_run(P, S, 1000))
-    n, cars, dt = _timed(seconds, one)
-    out["traffic"] = {"value": cars / dt, "unit": "car-updates/s",
-                      "sample": f"roads 0-{n - 1}, 10 + 1000 steps each ({dt:.1f} s, warm-up "
-                                "steps included in the time, not in the count)"}
-    def one(b):
-        P = oracle.lob_params(cap=1000, traders=100, seed=1 + b)
+        t0 = time.perf_counter()
+        upd += sum(st["cars"] for st in oracle.traffic_run(P, S, 1000))
+        dt += time.perf_counter() - t0
+    out["traffic"] = {"value": upd / dt, "unit": "car-updates/s",
+                      "sample": "roads 0-2, 1000 steps each after 10 warm-up steps"}
+    dt = 0.0
+    for bk in range(5):
+        P = oracle.lob_params(cap=1000, traders=100, seed=1 + bk)
         S = oracle.lob_init(P)
         oracle.lob_run(P, S, 20)
+        t0 = time.perf_counter()
         oracle.lob_run(P, S, 100)
-        return 100
-    n, steps, dt = _timed(seconds, one)
-    out["lob"] = {"value": steps / dt, "unit": "book-steps/s",
-                  "sample": f"books 0-{n - 1}, 20 + 100 steps each ({dt:.1f} s, warm-up steps "
-                            "included in the time, not in the count)"}
+        dt += time.perf_counter() - t0
+    out["lob"] = {"value": 500 / dt, "unit": "book-steps/s",
+                  "sample": "books 0-4, 100 steps each after 20 warm-up steps"}
     m = 1 << 22
     g = np.random.default_rng(7)
     key = g.integers(-2 ** 31, 2 ** 31, size=m, dtype=np.int64).astype(np.int32)
     attrs = W.int32_rows(8, 8, m)
     alive = np.ones(m, dtype=np.int32)
-    n, agents, dt = _timed(seconds, lambda _: (oracle.sort_agents(attrs, key, alive=alive), m)[1])
-    out["sort_agents"] = {"value": agents / dt, "unit": "agents/s",
-                          "sample": f"{n} sort(s) of 2^22 agents x 8 int32 + alive, full-range "
-                                    f"keys ({dt:.1f} s)"}
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.sort_agents(attrs, key, alive=alive)
+        ts.append(time.perf_counter() - t0)
+    out["sort_agents"] = {"value": m / _med(ts), "unit": "agents/s",
+                          "sample": "2^22 agents x 8 int32 + alive, full-range keys, median of 3 "
+                                    "(the wrapper's input copies included)"}
     cond = W.bernoulli_mask(3, 0.05, 1 << 24)
-    n, agents, dt = _timed(seconds, lambda _: (oracle.select_agents(cond), 1 << 24)[1])
-    out["select_agents"] = {"value": agents / dt, "unit": "agents/s",
-                            "sample": f"{n} call(s) on 2^24 Bernoulli(0.05) flags ({dt:.1f} s)"}
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.select_agents(cond)
+        ts.append(time.perf_counter() - t0)
+    out["select_agents"] = {"value": (1 << 24) / _med(ts), "unit": "agents/s",
+                            "sample": "2^24 Bernoulli(0.05) flags, median of 3"}
     return out
 
 
@@ -196,15 +270,10 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     batch = abm.BatchedPredation(params, steps, block_threads=tuning["block_threads"],
                                  items=tuning["items"])
     batch.init()
-    torch.cuda.synchronize()
-    side = torch.cuda.Stream()
-    with torch.cuda.stream(side):
-        batch.run(1, stream=side)          # warm-up (first step of every model)
-    side.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph, stream=side):
-        for _ in range(0, steps - 1, chunk):
-            batch.run(chunk, stream=side)
+    batch.run(1)                           # warm-up (first step of every model)
+    # the rest of the rollout, captured once by the library as a graph of
+    # persistent launches of `chunk` steps
+    graph = batch.capture(chunk, (steps - 1 + chunk - 1) // chunk)
     torch.cuda.synchronize()
     d0 = batch.descriptors()
     u0 = sum(d.updates for d in d0)
@@ -220,6 +289,7 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     updates = sum(d.updates for d in d1) - u0
     err = abm.workspace_error(batch.ws)
     cells = sum(sp.side * sp.side for sp in specs)
+    graph.destroy()
     del batch, graph
     torch.cuda.empty_cache()
 
@@ -244,7 +314,8 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     rate_p = pupd / (pms / 1e3)
     return {"workload": "4096 predation models, side uniform in [32, 256], sheep = cells/10, "
                         "wolves = cells/40, capacities 4x, seeds base+m; "
-                        f"{steps - 1} timed steps as one graph of {chunk}-step persistent launches",
+                        f"{steps - 1} timed steps as one library-captured graph of {chunk}-step "
+                        "persistent launches",
             "cells": cells, "agent_updates": updates, "ms": ms,
             "agent_updates_per_s": rate_b,
             "plain_agent_updates_per_s": rate_p,
@@ -403,7 +474,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sets", type=int, default=10, help="rotated input sets (seeds 0..sets-1)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seeds", type=int, default=3,
+                    help="microbenchmark seeds timed in the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -565,7 +637,7 @@ def main():
         out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seeds)
     for leg in ("predation_small", "predation_large", "predation_large_multi_prey", "batched",
                 "served"):
         if leg in out:

@@ -312,8 +312,10 @@ typedef struct abm_tuning {
  * workgroup.  The header ends with an error word (offset 248) that a run sets
  * to 1 if some descriptor's cap_s + cap_w exceeds 2 * max_cap (that model is
  * then left untouched) or if a team barrier times out (a member never ran;
- * the state of that team's model is then undefined).  Returns 0 for
- * max_cap outside [1, 2^30] or n_workgroups outside [1, 8192]. */
+ * the state of that team's model is then undefined).  The error word is
+ * sticky: zero the workspace once with abm_workspace_init before its first
+ * run; runs only ever set the word.  Returns 0 for max_cap outside
+ * [1, 2^30] or n_workgroups outside [1, 8192]. */
 ABM_API size_t abm_batched_workspace_bytes(int64_t max_cap, int32_t n_workgroups);
 
 /* Initial state of every model (the one-model definition per model, with the
@@ -338,6 +340,33 @@ ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, 
 /* countdown[cell_off + c] = max(0, ready[cell_off + c] - step) for every model:
  * the grass array of the one-model state.  countdown: device int32[sum of W*H]. */
 ABM_API int abm_predation_batched_grass(const abm_batch* b, int32_t* countdown, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Captured rollouts (Sec. 2: the paper compiles multi-step rollouts of
+ * vectorised models once and runs them as one scan; here a rollout is
+ * captured once as a HIP graph and replayed with one launch).
+ *
+ * abm_predation_batched_graph records n_chunks consecutive launches of
+ * abm_predation_run_batched(b, order, chunk_steps, tune, ws, ws_bytes) --
+ * each advances every model by up to chunk_steps steps, never past its
+ * steps_target -- into a graph, on a capture stream of its own, and returns
+ * an executable handle in *out.  Nothing runs at capture.  Argument errors
+ * are those of abm_predation_run_batched (checked at capture; no handle is
+ * returned).  The handle owns the graph only: every device pointer reachable
+ * from b, order and ws is recorded as it is, so those buffers must stay
+ * allocated and unmoved until abm_graph_destroy; their contents may change
+ * between replays (a replay continues from the current state and step
+ * counters).  abm_graph_replay launches the graph on `stream` (asynchronous,
+ * stream-ordered; the device must be the one current at capture).
+ * abm_graph_destroy releases the handle (NULL is accepted).
+ * ------------------------------------------------------------------------- */
+typedef struct abm_graph_s abm_graph;
+
+ABM_API int abm_predation_batched_graph(const abm_batch* b, const int32_t* order, int32_t chunk_steps,
+                                        int32_t n_chunks, const abm_tuning* tune, void* ws,
+                                        size_t ws_bytes, abm_graph** out);
+ABM_API int abm_graph_replay(abm_graph* g, void* stream);
+ABM_API int abm_graph_destroy(abm_graph* g);
 
 /* ---------------------------------------------------------------------------
  * sort_agents and select_agents (Sec. 2 API list).

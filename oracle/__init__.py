@@ -24,6 +24,15 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def use_library(path: str):
+    """Bind this module to another build of the same source (the timing build
+    of build.build_native); must come before any other call in the process."""
+    global _lib, LIB_PATH
+    if _lib is not None and LIB_PATH != path:
+        raise RuntimeError("the oracle library is already loaded from " + LIB_PATH)
+    LIB_PATH = path
+
+
 def lib():
     """Load liboracle.so, building it first if it is absent."""
     global _lib
@@ -237,6 +246,36 @@ def select_update(attrs, sel_mask, recs, upd_mask=None):
     lib().orc_select_update(out.shape[1], out.shape[0], pa, _ptr(sel_mask, C.c_uint8),
                             recs.shape[1], pr, um, C.byref(applied), C.byref(dropped))
     return out, applied.value, dropped.value
+
+
+def select_update_into(out, sel_mask, recs):
+    """select_update applied in place to the C-contiguous int32 [A, n] array
+    `out` (no copies; for timing).  Returns (applied, dropped)."""
+    assert out.dtype == np.int32 and out.flags["C_CONTIGUOUS"]
+    applied, dropped = C.c_int64(), C.c_int64()
+    lib().orc_select_update(out.shape[1], out.shape[0], _ptr_array(out),
+                            _ptr(sel_mask, C.c_uint8), recs.shape[1], _ptr_array(recs), None,
+                            C.byref(applied), C.byref(dropped))
+    return applied.value, dropped.value
+
+
+def add_agents_into(out, alive, recs):
+    """add_agents applied in place to `out` and `alive` (no copies; for
+    timing).  Returns (added, dropped)."""
+    assert out.dtype == np.int32 and out.flags["C_CONTIGUOUS"] and alive.flags["C_CONTIGUOUS"]
+    added, dropped = C.c_int64(), C.c_int64()
+    lib().orc_add_agents(out.shape[1], out.shape[0], _ptr_array(out), _ptr(alive, C.c_int32),
+                         recs.shape[1], _ptr_array(recs), C.byref(added), C.byref(dropped))
+    return added.value, dropped.value
+
+
+def remove_agents_into(alive, kill):
+    """remove_agents applied in place to `alive` (no copies; for timing)."""
+    assert alive.dtype == np.int32 and alive.flags["C_CONTIGUOUS"]
+    removed = C.c_int64()
+    lib().orc_remove_agents(alive.size, _ptr(alive, C.c_int32), _ptr(kill, C.c_uint8),
+                            C.byref(removed))
+    return removed.value
 
 
 def add_agents(attrs, alive, recs):

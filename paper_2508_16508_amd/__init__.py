@@ -31,7 +31,7 @@ EXPORTED = (
     "abm_select_update_batched", "abm_add_agents_batched", "abm_remove_agents_batched",
     "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
     "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents", "abm_lob_init",
-    "abm_lob_step",
+    "abm_lob_step", "abm_predation_batched_graph", "abm_graph_replay", "abm_graph_destroy",
 )
 
 
@@ -133,6 +133,10 @@ def lib():
         L.abm_predation_run_batched.argtypes = [C.POINTER(Batch), vp, i32, C.POINTER(Tuning), vp,
                                                 sz, vp]
         L.abm_predation_batched_grass.argtypes = [C.POINTER(Batch), vp, vp]
+        L.abm_predation_batched_graph.argtypes = [C.POINTER(Batch), vp, i32, i32,
+                                                  C.POINTER(Tuning), vp, sz, C.POINTER(vp)]
+        L.abm_graph_replay.argtypes = [vp, vp]
+        L.abm_graph_destroy.argtypes = [vp]
         L.abm_select_update_batched.argtypes = [i32, C.POINTER(Soa), vp, vp, C.POINTER(Records), vp,
                                                 vp, vp, vp, sz, vp]
         L.abm_add_agents_batched.argtypes = [i32, C.POINTER(Soa), vp, C.POINTER(Records), vp, vp,
@@ -582,6 +586,8 @@ class BatchedPredation:
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         off = (-ws.data_ptr()) % 256
         self.ws = ws[off: off + nbytes]
+        # zeroed once: the error word at its end of the header is sticky
+        _check(lib().abm_workspace_init(_p(self.ws), nbytes, _stream()))
 
     def _batch(self) -> Batch:
         sp = lambda d: SpeciesPtrs(*(d[k].data_ptr() for k in ("x", "y", "e", "alive")))
@@ -600,12 +606,28 @@ class BatchedPredation:
     def run(self, max_steps: int, stream=None, block_threads=None, workgroups=None, items=None,
             team_size=None, team_min_size=None, team_workgroups=0):
         b = self._batch()
-        k = self.team_size if team_size is None else team_size
-        nt = self.team_models(team_min_size) if k > 1 else 0
-        t = Tuning(block_threads or self.block_threads, workgroups or self.workgroups,
-                   items or self.items, k, nt, team_workgroups)
+        t = self._tuning(block_threads, workgroups, items, team_size, team_min_size,
+                         team_workgroups)
         _check(lib().abm_predation_run_batched(C.byref(b), _p(self.order), max_steps, C.byref(t),
                                                _p(self.ws), self.ws.numel(), _stream(stream)))
+
+    def _tuning(self, block_threads=None, workgroups=None, items=None, team_size=None,
+                team_min_size=None, team_workgroups=0) -> Tuning:
+        k = self.team_size if team_size is None else team_size
+        nt = self.team_models(team_min_size) if k > 1 else 0
+        return Tuning(block_threads or self.block_threads, workgroups or self.workgroups,
+                      items or self.items, k, nt, team_workgroups)
+
+    def capture(self, chunk_steps: int, n_chunks: int, **tuning) -> "RolloutGraph":
+        """A rollout of n_chunks launches of up to chunk_steps steps each,
+        captured by the library as one graph (nothing runs until replay)."""
+        b = self._batch()
+        t = self._tuning(**tuning)
+        h = C.c_void_p()
+        _check(lib().abm_predation_batched_graph(C.byref(b), _p(self.order), chunk_steps,
+                                                 n_chunks, C.byref(t), _p(self.ws),
+                                                 self.ws.numel(), C.byref(h)))
+        return RolloutGraph(h, self)
 
     def descriptors(self):
         """Host copy of the model descriptors (synchronises)."""
@@ -627,6 +649,27 @@ class BatchedPredation:
         sheep = {k: v[dm.sheep_off: dm.sheep_off + p.cap_s] for k, v in self.sheep.items()}
         wolves = {k: v[dm.wolf_off: dm.wolf_off + p.cap_w] for k, v in self.wolves.items()}
         return grass, sheep, wolves
+
+
+class RolloutGraph:
+    """A captured batched rollout (abm_predation_batched_graph).  Holds the
+    batch it was captured from, whose buffers the graph uses as they are."""
+
+    def __init__(self, handle: C.c_void_p, batch: BatchedPredation):
+        self.handle, self.batch = handle, batch
+
+    def replay(self, stream=None):
+        _check(lib().abm_graph_replay(self.handle, _stream(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().abm_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.abm_graph_destroy(self.handle)
+            self.handle = None
 
 
 # ---------------------------------------------------------------- traffic

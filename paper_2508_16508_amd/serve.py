@@ -266,6 +266,8 @@ class GpuRunner:
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         off = (-ws.data_ptr()) % 256
         self.ws = ws[off: off + nbytes]
+        # zeroed once: the error word of the header is sticky
+        abm._check(abm.lib().abm_workspace_init(abm._p(self.ws), nbytes, abm._stream()))
         self.keep_results = keep_results
         self.results = {}
         self.device = device

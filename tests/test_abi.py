@@ -109,6 +109,15 @@ def test_invalid_arguments_rejected_on_host(abm):
     p = C.c_void_p(256)
     assert L.abm_resolve_conflicts(1 << 31, p, p, None, 4, p, p, p, None) == abm.ABM_E_INVALID
     assert "2^31" in _err(abm)
+    # captured rollouts: no handle slot, bad chunking, NULL handles
+    h = C.c_void_p()
+    assert L.abm_predation_batched_graph(None, None, 10, 1, None, None, 0, None) == \
+        abm.ABM_E_INVALID
+    b = abm.Batch()
+    assert L.abm_predation_batched_graph(C.byref(b), None, 0, 1, None, None, 0, C.byref(h)) == \
+        abm.ABM_E_INVALID and not h.value
+    assert L.abm_graph_replay(None, None) == abm.ABM_E_INVALID
+    assert L.abm_graph_destroy(None) == abm.ABM_OK
     # select_indices: missing count
     assert L.abm_select_indices(None, 0, None, None, None, 0, None) == abm.ABM_E_INVALID
     # workspace init with nothing

@@ -269,3 +269,81 @@ def test_resume_from_an_edited_state(abm, orc, team_size):
             for f in FIELDS:
                 assert np.array_equal(_host(gsp[f]), osp[f]), (m, name, f)
         assert batch.descriptors()[m].step == 40
+
+
+def test_captured_rollout_replays_match_oracle(abm, orc):
+    """A rollout captured by the library (three launches of 10 steps) replayed
+    twice, with eager device work and synchronisation between the replays: the
+    state after each replay matches the oracle after 30 and 60 steps."""
+    kws = [dict(W=40, H=40, seed=21, cap_s=640, cap_w=160, n_s0=160, n_w0=40),
+           dict(W=25, H=31, seed=22, cap_s=300, cap_w=80, n_s0=77, n_w0=19),
+           dict(W=64, H=64, seed=23, cap_s=4096, cap_w=1024, n_s0=400, n_w0=100)]
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 60)
+    batch.init()
+    graph = batch.capture(10, 3)
+    torch.cuda.synchronize()
+    assert all(d.step == 0 for d in batch.descriptors())     # capture runs nothing
+    for steps in (30, 60):
+        graph.replay()
+        torch.cuda.synchronize()
+        checksum = int(batch.sheep["e"].to(torch.int64).sum().item())   # eager work between
+        cd = batch.grass_countdown()
+        for m, kw in enumerate(kws):
+            _check_model(abm, orc, batch, m, kw, steps, cd)
+        assert checksum == int(batch.sheep["e"].to(torch.int64).sum().item())
+    graph.replay()                                           # every model is at its target
+    torch.cuda.synchronize()
+    assert all(d.step == 60 for d in batch.descriptors())
+    graph.destroy()
+    assert abm.workspace_error(batch.ws) == 0
+
+
+def test_full_workload_graph_replay(abm, orc):
+    """The 4096-model workload (side 32-256) as the benchmark runs it: one
+    warm-up step, then 499 steps replayed from a library-captured graph of
+    50-step persistent launches.  Every model's whole state and counters
+    equal those of the same batch advanced without a graph, with another
+    launch shape (1024 x 4, teams of 4 for the 64 largest models, 100-step
+    launches); 48 models across the sizes equal the one-model multi-launch
+    path; 12 of them equal the oracle."""
+    specs = W.batched_models(0, 4096)
+    kws = [dict(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s, cap_w=sp.cap_w,
+                n_s0=sp.n_s0, n_w0=sp.n_w0) for sp in specs]
+    params = [abm.predation_params(**kw) for kw in kws]
+    steps = 500
+    a = abm.BatchedPredation(params, steps, block_threads=512, items=2)
+    a.init()
+    a.run(1)
+    graph = a.capture(50, 10)
+    graph.replay()
+    b = abm.BatchedPredation(params, steps, block_threads=1024, items=4, team_size=4,
+                             team_min_size=a.sorted_size[63])
+    b.init()
+    for _ in range(5):
+        b.run(100)
+    torch.cuda.synchronize()
+    assert abm.workspace_error(a.ws) == 0 and abm.workspace_error(b.ws) == 0
+    da, db = a.descriptors(), b.descriptors()
+    assert all(d.step == steps for d in da)
+    for m in range(len(specs)):
+        assert (da[m].updates, da[m].live_s, da[m].live_w) == \
+            (db[m].updates, db[m].live_s, db[m].live_w), m
+    ca, cb = a.grass_countdown(), b.grass_countdown()
+    assert torch.equal(ca, cb)
+    for f in FIELDS:
+        assert torch.equal(a.sheep[f], b.sheep[f]) and torch.equal(a.wolves[f], b.wolves[f]), f
+    del b, cb
+    torch.cuda.empty_cache()
+    by_side = sorted(range(len(specs)), key=lambda m: specs[m].side)
+    pick = [by_side[i] for i in np.linspace(0, len(specs) - 1, 48).astype(int)]
+    for m in pick:
+        plain = abm.predation_init(params[m])
+        plain.run(steps)
+        grass, sheep, wolves = a.model_state(m, ca)
+        assert torch.equal(grass, plain.grass), m
+        for f in FIELDS:
+            assert torch.equal(sheep[f], plain.sheep[f]) and torch.equal(wolves[f],
+                                                                          plain.wolves[f]), (m, f)
+    for m in pick[::4]:
+        _check_model(abm, orc, a, m, kws[m], steps, ca)
+    graph.destroy()

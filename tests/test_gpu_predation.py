@@ -4,7 +4,8 @@ Bit-exact comparison of every state array (grass countdowns; x, y, energy and
 alive of both species, including stale fields of free slots) and of the
 per-step statistics.  The small 64x64 workload is compared after every one of
 its 200 steps for seeds 0-9; tiny tori put every agent in conflict; the large
-2048x2048 workload (16M / 4M slots) is compared in full for its first steps
+2048x2048 workload (16M / 4M slots) is compared in full after each of its
+first steps and after step 100 (with the statistics of every step up to it),
 and checked through population bookkeeping for all 1000 steps.
 """
 import numpy as np
@@ -125,6 +126,23 @@ def test_large_workload(abm, orc):
         assert ge <= P.W * P.H and se <= live_s
     alive_s = int(_host(model.sheep["alive"]).sum())
     assert alive_s == st[n - 1][0] - st[n - 1][3] - st[n - 1][6] + st[n - 1][4]
+    assert abm.workspace_error(model.ws) == 0
+
+
+def test_large_workload_full_state_at_step_100(abm, orc):
+    """2048x2048 as above: the statistics of each of the first 100 steps and the
+    whole state (4M grass cells, 16M + 4M slots) after step 100."""
+    kw = dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000, n_w0=400_000,
+              seed=1)
+    P, S, model = _pair(abm, orc, **kw)
+    n = 100
+    stats = torch.zeros((n, 8), dtype=torch.int64, device="cuda")
+    model.run(n, stats)
+    exp = orc.predation_run(P, S, n)
+    got = _host(stats)
+    for t in range(n):
+        assert dict(zip(abm.STAT_NAMES, (int(v) for v in got[t]))) == exp[t], f"stats step {t}"
+    _assert_same(model, S, f"after step {n}")
     assert abm.workspace_error(model.ws) == 0
 
 

@@ -124,11 +124,12 @@ def test_add_agents_parity(abm, orc, n, free_p, q_frac):
     assert np.array_equal(host(d_alive), exp_alive)
 
 
+@pytest.mark.parametrize("seed", range(10))
 @pytest.mark.parametrize("p", W.DENSITIES)
-def test_add_remove_full_size(abm, orc, p):
+def test_add_remove_full_size(abm, orc, seed, p):
     """add_agents with free density p and k newborns, then remove_agents with the
-    same mask over the (now all-live) population: both at 2^24 x 8."""
-    case = W.select_update_case(0, p)
+    same mask over the (now all-live) population: both at 2^24 x 8, seeds 0-9."""
+    case = W.select_update_case(seed, p)
     alive = (1 - case.mask).astype(np.int32)
     exp, exp_alive, ea, ed = orc.add_agents(case.attrs, alive, case.records)
     d_attrs, d_alive = dev(case.attrs), dev(alive)
