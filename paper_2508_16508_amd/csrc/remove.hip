@@ -2,13 +2,17 @@
 // independent masked update with no ranking: alive[i] = 0 wherever kill[i].
 //
 // Each lane owns 32 consecutive slots: two 16-byte loads of the kill mask,
-// then, only for the 16-byte alive chunks holding a set kill byte, 16-byte
-// loads and stores of alive (a sparse kill mask touches only the alive lines
-// it needs).  The conditional accesses are buffer instructions whose offset is
-// moved out of range when not wanted -- the hardware then skips the access --
-// so there are no branches and all eight loads are in flight together.  Every
-// workgroup but the last publishes its removed count as an epoch-tagged status
-// word; the last one sums them (no same-address atomics, which serialise).
+// then, when one of its kill bytes is set, eight 16-byte loads and stores of
+// alive -- its whole 128-byte line (a sparse kill mask touches only the alive
+// lines it needs).  The line is always stored whole, the unchanged chunks with
+// the values they hold, because HBM3E has no byte mask: a partly written
+// sector costs the memory a read-modify-write, which a later kernel pays for
+// when the partly dirty line leaves the caches.  The conditional
+// accesses are buffer instructions whose offset is moved out of range when not
+// wanted -- the hardware then skips the access -- so there are no branches and
+// all eight loads are in flight together.  Every workgroup but the last
+// publishes its removed count as an epoch-tagged status word; the last one
+// sums them (no same-address atomics, which serialise).
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -22,6 +26,18 @@ constexpr int kBlock = 256;
 constexpr int kSlotsPerLane = 32;
 constexpr int kSkip = int(0x80000000u);   // out-of-range buffer offset: access skipped
 constexpr int64_t kSlotsPerBlock = int64_t(kBlock) * kSlotsPerLane;
+// 16-byte chunks per stored group: the lane's whole 128-byte line
+#ifndef ABM_REMOVE_GROUP_CHUNKS
+#define ABM_REMOVE_GROUP_CHUNKS 8
+#endif
+constexpr int kGroupChunks = ABM_REMOVE_GROUP_CHUNKS;
+static_assert(kGroupChunks == 1 || kGroupChunks == 2 || kGroupChunks == 4 || kGroupChunks == 8,
+              "group of 1, 2, 4 or 8 chunks");
+
+// Bits of the lane's eight chunks that share chunk q's group.
+__device__ __forceinline__ constexpr uint32_t group_of(int q) {
+    return ((1u << kGroupChunks) - 1u) << (q & ~(kGroupChunks - 1));
+}
 
 __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ kill,
                                                    int32_t* __restrict__ alive, int64_t n,
@@ -41,23 +57,30 @@ __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ k
         const uint4 k0 = kp[0], k1 = kp[1];
         const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
         const int lo = int(threadIdx.x) * kSlotsPerLane * 4;
+        uint32_t killc = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) killc |= uint32_t(kw[q] != 0u) << q;
         v4i al[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            al[q] = __builtin_amdgcn_raw_buffer_load_b128(ra, kw[q] ? lo + 16 * q : kSkip, 0, 0);
+            al[q] = __builtin_amdgcn_raw_buffer_load_b128(
+                ra, (killc & group_of(q)) ? lo + 16 * q : kSkip, 0, 0);
+        uint32_t changed = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            bool changed = false;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (((kw[q] >> (8 * b)) & 0xFFu) != 0u && al[q][b] != 0) {
                     ++removed;
                     al[q][b] = 0;
-                    changed = true;
+                    changed |= 1u << q;
                 }
             }
-            __builtin_amdgcn_raw_buffer_store_b128(al[q], ra, changed ? lo + 16 * q : kSkip, 0, 0);
         }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            __builtin_amdgcn_raw_buffer_store_b128(al[q], ra,
+                                                   (changed & group_of(q)) ? lo + 16 * q : kSkip, 0, 0);
     } else {
         for (int64_t s = first; s < n && s < first + kSlotsPerLane; ++s) {
             if (kill[s] != 0 && alive[s] != 0) {

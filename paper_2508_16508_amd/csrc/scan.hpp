@@ -47,6 +47,10 @@ constexpr uint32_t kEpochMask = 0x3FFFFFFFu;
 // predecessor that never publishes is a bug; the wait then ends, the missing
 // value counts as zero and *err is set, instead of hanging the device.
 constexpr uint32_t kSpinLimit = 1u << 21;
+// Pause between two polls of a status word (s_sleep units of 64 clocks).
+#ifndef ABM_POLL_SLEEP
+#define ABM_POLL_SLEEP 1
+#endif
 
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -99,7 +103,7 @@ __device__ __forceinline__ uint64_t poll_status(const uint64_t* p, uint64_t w, u
             st_agent(err, 1ull);
             return pack_status(epoch, kFlagPfx, 0u);
         }
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(ABM_POLL_SLEEP);
         w = ld_agent(p);
     }
     return w;

@@ -1,13 +1,22 @@
 // select.hip -- abm_select_update, abm_add_agents, abm_select_indices.
 //
 // One single-pass kernel per call: each tile ranks its selected slots (wave
-// ballot + mbcnt, LDS scan of wave totals, decoupled look-back), then every
-// selected slot of rank j < q PULLS record j and writes it into its own slot.
-// Pulling (the slot owner reads the record) rather than pushing means every
-// slot is written by the one thread that also read its mask/alive bit, so the
-// scatter needs no synchronisation beyond the rank itself.  This is the O(n)
-// counterpart of the paper's Rank-Match (Sec. 4, Alg. 1): the rank *is* the
-// index of the matching record, so no n x m candidate matrix or argmax is built.
+// ballot + mbcnt, LDS scan of wave totals, decoupled look-back), then the
+// selected slot of rank j < q receives record j.  The rank *is* the index of
+// the matching record, so this is the O(n) counterpart of the paper's
+// Rank-Match (Sec. 4, Alg. 1): no n x m candidate matrix or argmax is built.
+//
+// Writing the records.  HBM3E keeps ECC per 32-byte sector and has no byte
+// mask, so a store that covers part of a sector makes the memory read the
+// sector, merge and write it back -- and those read-modify-writes, issued in
+// random order, cost far more than streaming the same bytes.  The records are
+// therefore merged on the GPU: the tile walks its slots in 16-byte chunks with
+// consecutive threads on consecutive chunks, and every 32-byte sector that
+// holds a receiving slot is loaded, merged with its records and stored whole
+// (a sector whose slots all receive records is not loaded).  Sectors with no
+// receiving slot are neither read nor written.  Unselected slots of a touched
+// sector are rewritten with the values they hold, so no other writer may touch
+// the destination during the call (the same rule as for the selected slots).
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -39,7 +48,8 @@ struct SelArgs {
     uint64_t* status;
     EpochArg epoch;
     uint32_t ntiles;
-    int32_t n_attrs;
+    int32_t n_attrs;          // padded attribute count (1, 2, 4, 8 or 16)
+    int32_t n_true;           // attribute count
     int32_t vec_ok;           // mask / alive allow 16-byte loads
 };
 
@@ -79,14 +89,59 @@ __device__ __forceinline__ uint32_t load_bits(const SelArgs& a, int64_t first) {
     return bits;
 }
 
+// The scatter of k_select: the tile-local offsets of the selected slots sit in
+// pos[] in rank order, and consecutive threads walk those rank positions, so
+// the reads of records j, j+1, ... are contiguous and every load/store batch
+// is branch-free.  Two rank positions per thread and iteration (up to 32
+// loads in flight).  When the second position is past the end it aliases the
+// first: the same value goes to the same slot twice, which keeps the stores
+// unconditional.
+template <int MODE, int NA>
+__device__ __forceinline__ void scatter_tile(const SelArgs& a, const uint16_t* pos, int64_t tbase,
+                                             uint32_t tile_excl, uint32_t lim) {
+    for (uint32_t p0 = threadIdx.x; p0 < lim; p0 += 2 * kBlock) {
+        const uint32_t p1 = p0 + kBlock;
+        const bool has1 = p1 < lim;
+        const int64_t j0 = int64_t(tile_excl) + p0;
+        const int64_t j1 = int64_t(tile_excl) + (has1 ? p1 : p0);
+        const int64_t s0 = (MODE == kSelIndirect) ? a.rec_idx[j0] : j0;
+        const int64_t s1 = (MODE == kSelIndirect) ? a.rec_idx[j1] : j1;
+        const int64_t d0 = tbase + pos[p0];
+        const int64_t d1 = tbase + pos[has1 ? p1 : p0];
+        int32_t v0[NA], v1[NA];
+#pragma unroll
+        for (int at = 0; at < NA; ++at) {
+            v0[at] = a.rec[at][s0];
+            v1[at] = a.rec[at][s1];
+        }
+#pragma unroll
+        for (int at = 0; at < NA; ++at) {
+            a.dst[at][d0] = v0[at];
+            a.dst[at][d1] = v1[at];
+        }
+        if (MODE == kAddDense) {
+            a.alive[d0] = 1;
+            a.alive[d1] = 1;
+        }
+    }
+}
+
+// Tile-local offsets of this lane's selected slots (bits, from tile rank r),
+// written to pos[] in rank order.
+__device__ __forceinline__ void fill_pos(uint16_t* pos, uint32_t bits, uint32_t r) {
+    while (bits) {
+        const uint32_t k = __ffs(bits) - 1;
+        bits &= bits - 1;
+        pos[r++] = uint16_t(threadIdx.x * kSlotsPerLane + k);
+    }
+}
+
 // One tile of 8192 slots per block (a 2^24-slot launch is one round of
 // resident blocks).  Phase 1 ranks the tile's selected slots (lane-major: lane
 // t owns slots [32 t, 32 t + 32) of the tile) and writes their tile-local
-// offsets, in rank order, into LDS.  Phase 2 walks those rank positions with
-// consecutive threads, so the reads of records j, j+1, ... are contiguous and
-// every load/store batch is branch-free.  (Rewriting whole destination lines
-// instead would not pay: a partial 4-byte write costs the memory a line read
-// and write, but so does reading the line to fill in the unselected slots.)
+// offsets, in rank order, into LDS.  Phase 2 is scatter_tile.  This kernel
+// serves select_indices, and select_update / add_agents on destinations whose
+// arrays are not 16-byte aligned.
 //
 // NA is the attribute count rounded up to 1, 2, 4, 8 or 16; the host repeats
 // the last attribute's pointers in the padding entries (the repeated copy
@@ -117,44 +172,303 @@ __global__ __launch_bounds__(kBlock) void k_select(SelArgs a) {
         return;
     }
 
-    {
-        uint32_t bits = bits0, r = r0;
-        while (bits) {
-            const uint32_t k = __ffs(bits) - 1;
-            bits &= bits - 1;
-            pos[r++] = uint16_t(threadIdx.x * kSlotsPerLane + k);
-        }
-    }
+    fill_pos(pos, bits0, r0);
     __syncthreads();
     const int64_t q = (MODE == kSelIndirect) ? *a.d_q : a.q;
     const int64_t room = q - int64_t(tile_excl);
     const uint32_t lim = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
-    // Two rank positions per thread and iteration (up to 32 loads in flight).
-    // When the second position is past the end it aliases the first: the same
-    // value goes to the same slot twice, which keeps the stores unconditional.
-    for (uint32_t p0 = threadIdx.x; p0 < lim; p0 += 2 * kBlock) {
-        const uint32_t p1 = p0 + kBlock;
-        const bool has1 = p1 < lim;
-        const int64_t j0 = int64_t(tile_excl) + p0;
-        const int64_t j1 = int64_t(tile_excl) + (has1 ? p1 : p0);
-        const int64_t s0 = (MODE == kSelIndirect) ? a.rec_idx[j0] : j0;
-        const int64_t s1 = (MODE == kSelIndirect) ? a.rec_idx[j1] : j1;
-        const int64_t d0 = tbase + pos[p0];
-        const int64_t d1 = tbase + pos[has1 ? p1 : p0];
-        int32_t v0[NA], v1[NA];
+    scatter_tile<MODE, NA>(a, pos, tbase, tile_excl, lim);
+    if (tile == a.ntiles - 1 && threadIdx.x == 0) {
+        const int64_t p = int64_t(tile_excl) + total;
+        const int64_t rr = p < q ? p : q;
+        *a.d_applied = rr;
+        if (a.d_dropped) *a.d_dropped = q - rr;
+    }
+}
+
+// Line-list merge.  A lane of the rank phase owns 32 consecutive slots of the
+// tile, which are one 128-byte line of every attribute.  The lines holding a
+// receiving slot are compacted into a list in LDS; eight consecutive threads
+// then take one listed line (thread 8 i + k: chunk k, 16 bytes, of list entry
+// i), so a wave covers eight whole lines per instruction.  Each line is
+// loaded (a chunk whose four slots all receive is not), merged with its
+// records and stored whole; unlisted lines are never visited.
+constexpr int kLinesPerPass = 32;     // lines per work item (four chunk rows of a wave)
+
+__device__ __forceinline__ uint32_t low_bits(uint32_t k) { return k >= 32u ? ~0u : (1u << k) - 1u; }
+
+// The `keep` lowest set bits of b.
+__device__ __forceinline__ uint32_t lowest_set(uint32_t b, uint32_t keep) {
+    uint32_t out = 0;
+    for (uint32_t i = 0; i < keep; ++i) {
+        out |= b & (0u - b);
+        b &= b - 1u;
+    }
+    return out;
+}
+
+// The receiving slots among the selected bits `b` whose first selected slot
+// has tile rank `rk`: selected slots of rank < lim.  Ranks grow with the slot,
+// so these are the lowest set bits of b.
+__device__ __forceinline__ uint32_t receiving(uint32_t b, uint32_t rk, uint32_t lim,
+                                              uint32_t total) {
+    if (lim >= total) return b;
+    const uint32_t nb = __popc(b);
+    const uint32_t na = lim > rk ? (lim - rk < nb ? lim - rk : nb) : 0u;
+    return na == nb ? b : lowest_set(b, na);
+}
+
+// Descriptor of chunk k (slots 4k .. 4k+3) of a listed line with selection
+// bits `word` and first tile rank `pre`, packed into one word: the tile rank
+// of the chunk's first receiving slot (bits 0-15), its receiving slots (bits
+// 16-19, bit j = slot j of the chunk), valid (bit 20).
+constexpr uint32_t kValid = 1u << 20, kAll = 0xFu << 16;
+
+__device__ __forceinline__ uint32_t chunk_desc(uint32_t word, uint32_t pre, uint32_t k,
+                                               uint32_t lim, uint32_t total) {
+    const uint32_t sh = k << 2;
+    const uint32_t rk = pre + __popc(word & low_bits(sh));
+    const uint32_t ab = receiving((word >> sh) & 0xFu, rk, lim, total);
+    return rk | (ab << 16) | kValid;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kSkip = int(0x80000000u);     // out-of-range buffer offset: access skipped
+constexpr int kRsrcWord3 = 0x00020000;      // raw buffer descriptor, 32-bit data format
+
+// One work item of the line-list merge: attribute array `d` (ALIVE: the
+// alive array, merged with the constant 1).  The thread handles chunk t mod 8
+// of the lines at list entries i0 + j * istride (j < 4; entries past the list
+// are skipped): it loads the old values (not for a chunk whose four slots all receive), reads
+// the records of the receiving slots into them and stores the chunks whole.
+// All accesses are buffer instructions with 32-bit offsets from a per-tile
+// base (few registers); an access that is not wanted gets an out-of-range
+// offset, which the hardware skips (a skipped load returns 0).
+template <int MODE, bool ALIVE>
+__device__ __forceinline__ void merge_item(const SelArgs& a, int32_t* d, const int32_t* rec,
+                                           int64_t tbase, uint32_t tile_excl, uint32_t lim,
+                                           uint32_t total, uint32_t n_lines, uint32_t i0,
+                                           uint32_t istride, const uint16_t* list,
+                                           const uint32_t* wbits, const uint32_t* wpre) {
+    uint32_t dsc[4], off[4];
 #pragma unroll
-        for (int at = 0; at < NA; ++at) {
-            v0[at] = a.rec[at][s0];
-            v1[at] = a.rec[at][s1];
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t i = i0 + uint32_t(j) * istride;
+        const uint32_t k = threadIdx.x & 7u;
+        const uint32_t line = i < n_lines ? list[i] : 0u;
+        dsc[j] = i < n_lines ? chunk_desc(wbits[line], wpre[line], k, lim, total) : 0u;
+        off[j] = (line * 8u + k) * 16u;
+    }
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc(d + tbase, 0, int(kTile * 4), kRsrcWord3);
+    v4i v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool need = (dsc[j] & kValid) && (dsc[j] & kAll) != kAll;
+        v[j] = __builtin_amdgcn_raw_buffer_load_b128(rd, need ? int(off[j]) : kSkip, 0, 0);
+    }
+    if (ALIVE) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ab = (dsc[j] >> 16) & 0xFu;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((ab >> k) & 1u) v[j][k] = 1;
+        }
+    } else {
+        const int32_t* rt = rec + (MODE == kSelIndirect ? 0 : int64_t(tile_excl));
+        const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int32_t*>(rt), 0, int(lim * 4u), kRsrcWord3);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ab = (dsc[j] >> 16) & 0xFu, rk = dsc[j] & 0xFFFFu;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool on = (ab >> k) & 1u;
+                const uint32_t r = rk + __popc(ab & low_bits(uint32_t(k)));
+                int32_t x;
+                if (MODE == kSelIndirect)
+                    x = on ? rt[a.rec_idx[int64_t(tile_excl) + r]] : 0;
+                else
+                    x = __builtin_amdgcn_raw_buffer_load_b32(rr, on ? int(r * 4u) : kSkip, 0, 0);
+                if (on) v[j][k] = x;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        __builtin_amdgcn_raw_buffer_store_b128(v[j], rd, (dsc[j] & kValid) ? int(off[j]) : kSkip,
+                                               0, 0);
+}
+
+// One array of a dense tile: the thread's chunks are list entries 32 j + t / 8
+// (j < 8) with descriptors and offsets precomputed in dsc / off; batches of
+// four (loads, record reads, stores), `rows` of the eight being in use.
+template <int MODE, bool ALIVE>
+__device__ __forceinline__ void merge_dense(const SelArgs& a, int32_t* d, const int32_t* rec,
+                                            int64_t tbase, uint32_t tile_excl, uint32_t lim,
+                                            uint32_t (&dsc)[8], uint32_t (&off)[8], int rows) {
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc(d + tbase, 0, int(kTile * 4), kRsrcWord3);
+    const int32_t* rt = ALIVE ? nullptr
+                              : rec + (MODE == kSelIndirect ? 0 : int64_t(tile_excl));
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t*>(rt), 0, ALIVE ? 0 : int(lim * 4u), kRsrcWord3);
+#pragma unroll
+    for (int jb = 0; jb < 8; jb += 4) {
+        if (jb >= rows) break;
+        // the values below are the same for every array; recomputing them per
+        // array keeps the compiler from holding all of them in registers
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            asm volatile("" : "+v"(dsc[jb + j]));
+            asm volatile("" : "+v"(off[jb + j]));
+        }
+        v4i v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t dd = dsc[jb + j];
+            const bool need = (dd & kValid) && (dd & kAll) != kAll;
+            v[j] = __builtin_amdgcn_raw_buffer_load_b128(rd, need ? int(off[jb + j]) : kSkip, 0, 0);
         }
 #pragma unroll
-        for (int at = 0; at < NA; ++at) {
-            a.dst[at][d0] = v0[at];
-            a.dst[at][d1] = v1[at];
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ab = (dsc[jb + j] >> 16) & 0xFu, rk = dsc[jb + j] & 0xFFFFu;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool on = (ab >> k) & 1u;
+                int32_t x = 1;
+                if (!ALIVE) {
+                    const uint32_t r = rk + __popc(ab & low_bits(uint32_t(k)));
+                    if (MODE == kSelIndirect)
+                        x = on ? rt[a.rec_idx[int64_t(tile_excl) + r]] : 0;
+                    else
+                        x = __builtin_amdgcn_raw_buffer_load_b32(rr, on ? int(r * 4u) : kSkip,
+                                                                 0, 0);
+                }
+                if (on) v[j][k] = x;
+            }
         }
-        if (MODE == kAddDense) {
-            a.alive[d0] = 1;
-            a.alive[d1] = 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            __builtin_amdgcn_raw_buffer_store_b128(
+                v[j], rd, (dsc[jb + j] & kValid) ? int(off[jb + j]) : kSkip, 0, 0);
+    }
+}
+
+// The listed lines of a full tile, every attribute (and, for add_agents,
+// alive = 1 as one more).  A dense tile (more than 96 listed lines) runs the
+// arrays one after another with the whole block on each: thread t takes list
+// entries 32 j + t / 8 (j < 8, in two batches of four), so the four waves work
+// on neighbouring lines of one array.  A sparse tile would then leave each
+// wave a chain of one memory round trip per array; instead its work is cut
+// into items of (array, 32 listed lines), wave w taking items w, w + 4, ...,
+// so its arrays are in flight on the four waves at once.
+template <int MODE>
+__device__ __forceinline__ void merge_tile(const SelArgs& a, int64_t tbase, uint32_t tile_excl,
+                                           uint32_t lim, uint32_t total, uint32_t n_lines,
+                                           const uint16_t* list, const uint32_t* wbits,
+                                           const uint32_t* wpre) {
+    const int n_arr = a.n_true + (MODE == kAddDense ? 1 : 0);
+    if (n_lines > 3 * kLinesPerPass) {
+        uint32_t dsc[8], off[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t i = uint32_t(j * kLinesPerPass) + (threadIdx.x >> 3);
+            const uint32_t k = threadIdx.x & 7u;
+            const uint32_t line = i < n_lines ? list[i] : 0u;
+            dsc[j] = i < n_lines ? chunk_desc(wbits[line], wpre[line], k, lim, total) : 0u;
+            off[j] = (line * 8u + k) * 16u;
+        }
+        const int rows = int((n_lines + kLinesPerPass - 1) / kLinesPerPass);
+        for (int at = 0; at < a.n_true; ++at)
+            merge_dense<MODE, false>(a, a.dst[at], a.rec[at], tbase, tile_excl, lim, dsc, off,
+                                     rows);
+        if (MODE == kAddDense)
+            merge_dense<MODE, true>(a, a.alive, nullptr, tbase, tile_excl, lim, dsc, off, rows);
+        return;
+    }
+    // the wave index is uniform in the wave; said explicitly, so that the
+    // array pointers picked by it stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int batches = int((n_lines + kLinesPerPass - 1) / kLinesPerPass);
+    const int items = n_arr * batches;
+    for (int it = wave; it < items; it += kWaves) {
+        const int at = it / batches, b = it - at * batches;
+        const uint32_t i0 = uint32_t(b * kLinesPerPass) + ((threadIdx.x & 63u) >> 3);
+        if (MODE == kAddDense && at == a.n_true)
+            merge_item<MODE, true>(a, a.alive, nullptr, tbase, tile_excl, lim, total, n_lines, i0,
+                                   8, list, wbits, wpre);
+        else
+            merge_item<MODE, false>(a, a.dst[at], a.rec[at], tbase, tile_excl, lim, total,
+                                    n_lines, i0, 8, list, wbits, wpre);
+    }
+}
+
+// select_update / add_agents with whole-line writes.  The rank phase is that
+// of k_select (lane t owns slots [32 t, 32 t + 32) of the 8192-slot tile,
+// line t of every attribute); the merge is the line-list merge above, applied
+// to every attribute and, for add_agents, to alive with the constant 1 (see
+// merge_tile).  Every
+// pointer is 16-byte aligned (checked on the host); the last tile, when
+// partial, writes slot by slot.  The kernel stays within 64 VGPRs, so all
+// 2048 tiles of a 2^24-slot launch are resident at once and the look-back
+// waits one round.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_merge(SelArgs a) {
+    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t wbits[kBlock];
+    __shared__ uint32_t wpre[kBlock];
+    __shared__ uint16_t list[kBlock];
+    __shared__ uint32_t lcount[kWaves];
+    const uint32_t tile = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t epoch = read_epoch(a.epoch);
+    const int64_t tbase = int64_t(tile) * kTile;
+    const int64_t lbase = tbase + int64_t(threadIdx.x) * kSlotsPerLane;
+    const bool full_tile = tbase + kTile <= a.n;
+    const uint32_t bits0 = load_bits<MODE>(a, lbase);
+
+    uint32_t r0, total;
+    uint32_t tile_excl = rank_counts<kWaves>(__popc(bits0), &r0, a.status, a.status - 1, tile,
+                                             a.ntiles, epoch, lds, &total);
+    // the tile's prefix and count are the same in every lane (read from LDS):
+    // say so, so that the buffer descriptors built from them stay scalar
+    tile_excl = __builtin_amdgcn_readfirstlane(tile_excl);
+    total = __builtin_amdgcn_readfirstlane(total);
+    const int64_t q = (MODE == kSelIndirect) ? *a.d_q : a.q;
+    const int64_t room = q - int64_t(tile_excl);
+    const uint32_t lim = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
+
+    // compact the lines holding a receiving slot (in line order)
+    const bool listed = bits0 != 0u && r0 < lim;
+    const uint64_t bal = __ballot(listed);
+    wbits[threadIdx.x] = bits0;
+    wpre[threadIdx.x] = r0;
+    if (lane == 0) lcount[wave] = uint32_t(__popcll(bal));
+    __syncthreads();
+    uint32_t before = 0, n_lines = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = lcount[w];
+        before += w < wave ? c : 0u;
+        n_lines += c;
+    }
+    n_lines = __builtin_amdgcn_readfirstlane(n_lines);
+    if (listed) list[before + lane_rank(bal)] = uint16_t(threadIdx.x);
+    __syncthreads();
+
+    if (lim > 0 && full_tile) {
+        merge_tile<MODE>(a, tbase, tile_excl, lim, total, n_lines, list, wbits, wpre);
+    } else if (lim > 0 && listed) {
+        // partial last tile: this lane's own receiving slots, one by one
+        const uint32_t ab = receiving(bits0, r0, lim, total);
+        for (uint32_t k = 0; k < 32; ++k) {
+            if (!((ab >> k) & 1u)) continue;
+            const int64_t g = int64_t(tile_excl) + r0 + __popc(ab & low_bits(k));
+            const int64_t r = (MODE == kSelIndirect) ? int64_t(a.rec_idx[g]) : g;
+            for (int at = 0; at < a.n_true; ++at) a.dst[at][lbase + k] = a.rec[at][r];
+            if (MODE == kAddDense) a.alive[lbase + k] = 1;
         }
     }
     if (tile == a.ntiles - 1 && threadIdx.x == 0) {
@@ -213,6 +527,7 @@ void fill_attrs(SelArgs& a, const abm_soa* dst, const abm_records* rec) {
         a.rec[i] = rec->attr[src];
     }
     a.n_attrs = na;
+    a.n_true = n;
 }
 
 template <int MODE>
@@ -225,6 +540,19 @@ void launch_select(const SelArgs& a, hipStream_t st) {
         case 8: hipLaunchKernelGGL((k_select<MODE, 8>), grid, block, 0, st, a); break;
         default: hipLaunchKernelGGL((k_select<MODE, 16>), grid, block, 0, st, a); break;
     }
+}
+
+// The merging kernel when every destination (and alive) pointer allows
+// 16-byte access, else the scattering one.
+template <int MODE>
+void launch_write(SelArgs a, const abm_soa* dst, hipStream_t st) {
+    bool vec = MODE != kAddDense || aligned16(dst->alive);
+    for (int i = 0; i < dst->n_attrs; ++i) vec = vec && aligned16(dst->attr[i]);
+    if (!vec) {
+        launch_select<MODE>(a, st);
+        return;
+    }
+    hipLaunchKernelGGL((k_merge<MODE>), dim3(a.ntiles), dim3(kBlock), 0, st, a);
 }
 
 int launch_compact(const uint8_t* mask, int64_t n, int32_t* out, int64_t* d_count,
@@ -294,9 +622,9 @@ extern "C" int abm_select_update(const abm_soa* dst, const uint8_t* sel_mask,
     rc = next_epoch(w, st, &a.epoch);
     if (rc != ABM_OK) return rc;
     if (d_q)
-        launch_select<kSelIndirect>(a, st);
+        launch_write<kSelIndirect>(a, dst, st);
     else
-        launch_select<kSelDense>(a, st);
+        launch_write<kSelDense>(a, dst, st);
     return launch_status("select_update");
 }
 
@@ -330,7 +658,7 @@ extern "C" int abm_add_agents(const abm_soa* dst, const abm_records* newborn, in
     a.vec_ok = aligned16(dst->alive);
     rc = next_epoch(w, st, &a.epoch);
     if (rc != ABM_OK) return rc;
-    launch_select<kAddDense>(a, st);
+    launch_write<kAddDense>(a, dst, st);
     return launch_status("add_agents");
 }
 
