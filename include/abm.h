@@ -110,6 +110,26 @@ ABM_API int abm_select_update(const abm_soa* dst, const uint8_t* sel_mask, const
                       void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * abm_select_update_noalloc -- abm_select_update (dense records: every record
+ * is selected, as with upd_mask == NULL) for callers that cannot allocate:
+ * code under stream capture, tight serving loops, harnesses that forbid
+ * device allocation.  It takes no workspace and allocates nothing; its scan
+ * state lives in a static device array of the library (under 512 KiB per
+ * device, held until the process ends).  Same semantics, arguments and
+ * results as abm_select_update, plus:
+ *   dst->capacity  at most 2^28 slots, else ABM_E_INVALID before any launch.
+ *   d_error        device int64 or NULL: receives 1 if a bounded wait of the
+ *                  scan gave up since the last call that passed d_error (the
+ *                  results are then invalid; never expected), else 0.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, or host threads) race and give wrong
+ * results; serialise them.
+ * ------------------------------------------------------------------------- */
+ABM_API int abm_select_update_noalloc(const abm_soa* dst, const uint8_t* sel_mask,
+                                      const abm_records* upd, int64_t* d_applied,
+                                      int64_t* d_dropped, int64_t* d_error, void* stream);
+
+/* ---------------------------------------------------------------------------
  * abm_select_indices -- the paper's select_agents (Sec. 2): the ascending
  * indices of the selected slots and their number.
  *   mask       device uint8[n].

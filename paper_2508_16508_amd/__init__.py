@@ -32,6 +32,7 @@ EXPORTED = (
     "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
     "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents", "abm_lob_init",
     "abm_lob_step", "abm_predation_batched_graph", "abm_graph_replay", "abm_graph_destroy",
+    "abm_select_update_noalloc",
 )
 
 
@@ -120,6 +121,8 @@ def lib():
         L.abm_select_update.argtypes = [C.POINTER(Soa), vp, C.POINTER(Records), vp, vp, vp, vp,
                                         sz, vp]
         L.abm_select_indices.argtypes = [vp, i64, vp, vp, vp, sz, vp]
+        L.abm_select_update_noalloc.argtypes = [C.POINTER(Soa), vp, C.POINTER(Records), vp, vp,
+                                                vp, vp]
         L.abm_add_agents.argtypes = [C.POINTER(Soa), C.POINTER(Records), vp, vp, vp, sz, vp]
         L.abm_remove_agents.argtypes = [C.POINTER(Soa), vp, vp, vp, sz, vp]
         L.abm_resolve_conflicts.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, vp]
@@ -261,6 +264,20 @@ def select_update(attrs, sel_mask, recs, upd_mask=None, ws=None, applied=None, d
     _check(lib().abm_select_update(C.byref(dst), _p(sel_mask), C.byref(upd), _p(upd_mask),
                                    _p(applied), _p(dropped), _p(ws), ws.numel(), _stream(stream)))
     return applied, dropped
+
+
+def select_update_noalloc(attrs, sel_mask, recs, applied=None, dropped=None, error=None,
+                          stream=None):
+    """select_update with dense records and no workspace (the library's
+    static scan state; at most 2^28 slots; calls on one device must not
+    overlap).  Returns (applied, dropped, error) device int64 tensors."""
+    dst = make_soa(attrs)
+    upd = make_records(recs)
+    _require(sel_mask, torch.uint8, "sel_mask")
+    applied, dropped, error = _counts(sel_mask.device, applied, dropped, error)
+    _check(lib().abm_select_update_noalloc(C.byref(dst), _p(sel_mask), C.byref(upd), _p(applied),
+                                           _p(dropped), _p(error), _stream(stream)))
+    return applied, dropped, error
 
 
 def select_indices(mask, out_idx=None, ws=None, count=None, stream=None):

@@ -19,6 +19,8 @@
 // the destination during the call (the same rule as for the selected slots).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "abm.h"
 #include "common.hpp"
 #include "scan.hpp"
@@ -555,6 +557,58 @@ void launch_write(SelArgs a, const abm_soa* dst, hipStream_t st) {
     hipLaunchKernelGGL((k_merge<MODE>), dim3(a.ntiles), dim3(kBlock), 0, st, a);
 }
 
+// ------------------------------------------------------------ no-allocation form
+// The scan state of abm_select_update_noalloc lives in this array: a 256-byte
+// header (epoch word, error word at byte 248) followed by the tile status
+// words of one scan chain for up to kNoallocMaxSlots slots.  Each device holds
+// its own copy for the life of the process; every call on a device shares it.
+constexpr int64_t kNoallocMaxSlots = int64_t(1) << 28;
+// status words of one chain of T tiles: the tile words and each level's group
+// words (as laid out by hier_prefix)
+constexpr int64_t chain_words_c(int64_t T, int levels) {
+    return levels == 0 ? 0 : T + chain_words_c((T + 63) / 64, levels - 1);
+}
+constexpr int64_t kScratchWords =
+    kHeaderBytes / 8 + chain_words_c((kNoallocMaxSlots + kTile - 1) / kTile, kLevels) + 8;
+static_assert(kScratchWords * 8 < (int64_t(1) << 19), "scratch stays under 512 KiB");
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kScratchDevices] = {};
+
+// Device address of this device's `scratch` (looked up once per device, with
+// the device current; the array's host-side name is not a device address).
+int scratch_for_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("hipGetDevice: %s", hipGetErrorString(e));
+        return ABM_E_HIP;
+    }
+    if (dev < 0 || dev >= kScratchDevices) return fail(ABM_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return ABM_E_HIP;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return ABM_OK;
+}
+
+// Hands the scratch error word to the caller and clears it for the next call.
+__global__ void k_take_error(uint64_t* word, int64_t* d_error) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *d_error = int64_t(*word);
+        *word = 0;
+    }
+}
+
 int launch_compact(const uint8_t* mask, int64_t n, int32_t* out, int64_t* d_count,
                    const Workspace& w, hipStream_t st) {
     SelArgs c = {};
@@ -679,4 +733,50 @@ extern "C" int abm_select_indices(const uint8_t* mask, int64_t n, int32_t* out_i
         return launch_status("select_indices");
     }
     return launch_compact(mask, n, out_idx, d_count, w, st);
+}
+
+extern "C" int abm_select_update_noalloc(const abm_soa* dst, const uint8_t* sel_mask,
+                                         const abm_records* upd, int64_t* d_applied,
+                                         int64_t* d_dropped, int64_t* d_error, void* stream) {
+    int rc = check_soa(dst, false);
+    if (rc != ABM_OK) return rc;
+    rc = check_records(upd, dst->n_attrs);
+    if (rc != ABM_OK) return rc;
+    if (!d_applied) return fail(ABM_E_INVALID, "d_applied is NULL");
+    if (dst->capacity > 0 && !sel_mask) return fail(ABM_E_INVALID, "sel_mask is NULL");
+    if (dst->capacity > kNoallocMaxSlots) {
+        set_error("capacity %lld exceeds the no-allocation maximum of 2^28 slots",
+                  static_cast<long long>(dst->capacity));
+        return ABM_E_INVALID;
+    }
+    rc = check_device();
+    if (rc != ABM_OK) return rc;
+    void* base = nullptr;
+    rc = scratch_for_device(&base);
+    if (rc != ABM_OK) return rc;
+    Workspace w = {};
+    w.hdr = static_cast<uint64_t*>(base);
+    w.status = w.hdr + kHeaderBytes / 8;
+    hipStream_t st = as_stream(stream);
+    if (dst->capacity == 0 || upd->count == 0) {
+        hipLaunchKernelGGL(k_counts, dim3(1), dim3(64), 0, st, nullptr, upd->count, d_applied,
+                           d_dropped);
+    } else {
+        SelArgs a = {};
+        fill_attrs(a, dst, upd);
+        a.mask = sel_mask;
+        a.q = upd->count;
+        a.n = dst->capacity;
+        a.d_applied = d_applied;
+        a.d_dropped = d_dropped;
+        a.status = w.status;
+        a.ntiles = static_cast<uint32_t>(tiles_for(dst->capacity, kTile));
+        a.vec_ok = aligned16(sel_mask);
+        rc = next_epoch(w, st, &a.epoch);
+        if (rc != ABM_OK) return rc;
+        launch_write<kSelDense>(a, dst, st);
+    }
+    if (d_error)
+        hipLaunchKernelGGL(k_take_error, dim3(1), dim3(64), 0, st, w.hdr + kHdrError, d_error);
+    return launch_status("select_update_noalloc");
 }
