@@ -42,6 +42,7 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // [.., + 4*C)              int32 index list (compacted record indices or breeders)
 // [.., + 4*C)              second int32 index list (second species)
 // [.., + 8*kAccWords)      int64 spread accumulators (kAccLanes per counter)
+// [.., + 2 * bitmask)      two live-slot bitmasks (predation: sheep, wolves)
 // S covers two chains of ceil(C / kMinTile) tiles each.
 constexpr int64_t kHeaderBytes = 256;
 constexpr int64_t kMinTile = 512;
@@ -65,9 +66,14 @@ inline int64_t status_words(int64_t capacity) {
     return 2 * (t + t / 63 + 8) + 2;
 }
 
+// Live-slot bitmask of one collection of up to `capacity` slots: one bit per
+// slot, padded to whole 8192-slot tiles (1 KiB each).
+inline int64_t bitmask_bytes(int64_t capacity) { return tiles_for(capacity, 8192) * 1024; }
+
 inline size_t workspace_bytes(int64_t capacity) {
     if (capacity < 1) capacity = 1;
-    return (size_t)(kHeaderBytes + 8 * status_words(capacity) + 8 * capacity + 8 * kAccWords + 64);
+    return (size_t)(kHeaderBytes + 8 * status_words(capacity) + 8 * capacity + 8 * kAccWords +
+                    2 * bitmask_bytes(capacity) + 64);
 }
 
 struct Workspace {
@@ -76,6 +82,8 @@ struct Workspace {
     int32_t* list_a;
     int32_t* list_b;
     int64_t* acc;
+    uint32_t* bits_a;   // live-slot bitmasks (predation: sheep, wolves)
+    uint32_t* bits_b;
 };
 
 inline Workspace carve(void* ws, int64_t capacity) {
@@ -88,6 +96,8 @@ inline Workspace carve(void* ws, int64_t capacity) {
     w.list_a = reinterpret_cast<int32_t*>(lists);
     w.list_b = reinterpret_cast<int32_t*>(lists + 4 * capacity);
     w.acc = reinterpret_cast<int64_t*>(lists + 8 * capacity);
+    w.bits_a = reinterpret_cast<uint32_t*>(lists + 8 * capacity + 8 * kAccWords);
+    w.bits_b = w.bits_a + bitmask_bytes(capacity) / 4;
     return w;
 }
 

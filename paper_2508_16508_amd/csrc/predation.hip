@@ -1,29 +1,40 @@
 // predation.hip -- abm_predation_init / abm_predation_step: the wolf-sheep-
 // grass model of Sec. 5.1 (Fig. 2) on one GPU, one model per launch sequence.
 //
-// Step t is four launches (each arrow is a grid-wide dependency):
+// Inside a call the state is kept in two working forms (converted at the call's
+// start and back at its end): grass holds the step at which a cell is grown
+// again (grown at step t iff ready <= t), so no per-step regrow pass is needed,
+// and a bitmask in the workspace marks the live slots, so the per-step kernels
+// read 1 bit per slot instead of the 4-byte alive word and visit only live
+// agents.  Each kernel works on tiles of 8192 slots (256 threads, thread t
+// owning the 32 slots of bitmask word t); a tile first compacts its live slots
+// into a list in LDS and then spreads that list over all its threads, four
+// agents per thread in flight, so dense and sparse tiles alike keep every
+// lane busy.  Step t is three launches (each arrow a grid-wide dependency):
 //   K1 move+claim   every live agent moves, pays 1 energy and posts its
 //                   packed (draw << 32 | slot) key with a 64-bit atomicMin into
 //                   the claim tables of its cell: grass (sheep on grown
 //                   cells), prey (sheep) and eater (wolves).
 //   K2 eat+breeders each live agent compares its keys with the reduced table
 //                   entries (grass winner, eaten sheep, eating wolf), applies
-//                   the energy gain / death, then decides whether it breeds;
-//                   breeders are compacted into an ascending list with the
-//                   single-pass scan (one scan chain per species).
-//   K3 breed+die    free slots (alive == 0) are ranked by the same scan; the
-//                   free slot of rank j < #breeders PULLS its child from
-//                   breeder j (cell, half the energy) and the parent keeps the
-//                   rest; live agents with negative energy die.
-//   K4 regrow       every countdown above zero drops by one and the claim
-//                   tables are re-armed for the next step.
+//                   the energy gain and marks an eaten sheep alive = 2, then
+//                   decides whether it breeds; breeders are compacted into an
+//                   ascending list with the single-pass scan (one scan chain
+//                   per species).
+//   K3 breed+die    the claim tables are re-armed for the next step (each
+//                   workgroup streams its slice); free slots (alive == 0, or
+//                   eaten this step) are ranked by the same scan, and the free
+//                   slot of rank j <
+//                   #breeders PULLS its child from breeder j (cell, half the
+//                   energy) while the parent keeps the rest; live agents with
+//                   negative energy die.
 // With multi_prey, K1 instead pushes every live sheep and wolf onto a list of
 // its cell (64-bit atomicExch on the prey / eater words, which then hold list
 // heads), and K1b, between K1 and K2, pairs the r-th wolf of each cell (eat
 // key order) with the r-th sheep (prey key order): the wolf gains, the sheep
 // is marked alive = 2 (eaten, still to take part in the grass rule of K2).
 // Pulling into the free slot (rather than the parent pushing into some later
-// tile) keeps every slot written by the thread that ranked it.
+// tile) keeps every slot written by one thread.
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -35,9 +46,12 @@ namespace abm {
 namespace {
 
 constexpr int kWaves = 4;
-constexpr int kItems = 16;
-constexpr int64_t kTile = int64_t(kWaves) * 64 * kItems;
 constexpr int kBlock = 256;
+constexpr int64_t kTile = int64_t(kBlock) * 32;   // 8192 slots: one bitmask word per thread
+#ifndef ABM_PRED_IN_FLIGHT
+#define ABM_PRED_IN_FLIGHT 4
+#endif
+constexpr int kInFlight = ABM_PRED_IN_FLIGHT;      // list entries per thread and batch
 constexpr uint64_t kNoClaim = ~0ull;
 
 // Offsets of the eight neighbours, indexed by dir = draw >> 29, packed as
@@ -61,9 +75,12 @@ struct StepArgs {
     int32_t W, H, R, gain_s, gain_w;
     uint32_t T_s, T_w, seed;
     int64_t cap_s, cap_w;
-    int32_t* grass;
+    int32_t* ready;       // grass: step at which each cell is grown again
     Species sp[2];        // 0 sheep, 1 wolves
-    uint64_t* gclaim;     // grass: lowest sheep key per grown cell
+    uint32_t* bits[2];    // live-slot bitmasks
+    int64_t G;            // cells
+    uint64_t* gclaim;     // grass: lowest sheep key per grown cell (the three
+                          // tables are consecutive: gclaim, sclaim, wclaim)
     uint64_t* sclaim;     // prey: lowest sheep key per cell
     uint64_t* wclaim;     // eater: lowest wolf key per cell
     int64_t* stats;       // this step's row of 8, or null
@@ -159,51 +176,151 @@ __global__ __launch_bounds__(kBlock) void k_fill64(int64_t* p, int64_t n, int64_
     if (i < n) p[i] = v;
 }
 
+// ------------------------------------------------------------------ tiles
+// Tile t of a species covers slots [8192 t, 8192 t + 8192) and bitmask words
+// [256 t, 256 t + 256), thread k owning word 256 t + k (slots 32 k .. 32 k + 31
+// of the tile).  Bits of slots at or beyond the capacity are always zero.
+// Workgroups take the tiles of both species interleaved -- sheep 0, wolves 0,
+// sheep 1, wolves 1, ... until the shorter chain ends, then the rest of the
+// longer one -- so that the low tiles, where children fill the lowest free
+// slots and the live agents gather, are all in the first round of resident
+// workgroups; within each chain tiles still run in increasing order.
+struct TileRef {
+    int s;            // species
+    uint32_t tile;    // tile within the species' scan chain
+    int64_t base;     // first slot
+};
+
+__device__ __forceinline__ TileRef tile_of(const StepArgs& a) {
+    const uint32_t m = a.tiles[0] < a.tiles[1] ? a.tiles[0] : a.tiles[1];
+    const uint32_t b = blockIdx.x;
+    TileRef r;
+    if (b < 2 * m) {
+        r.s = int(b & 1u);
+        r.tile = b >> 1;
+    } else {
+        r.s = a.tiles[0] > a.tiles[1] ? 0 : 1;
+        r.tile = m + (b - 2 * m);
+    }
+    r.base = int64_t(r.tile) * kTile;
+    return r;
+}
+
+// Block-wide list, in slot order, of the tile offsets of the set bits of each
+// thread's mask (thread t owns offsets 32 t .. 32 t + 31).  Returns the list
+// length (the same in every thread); *first receives the list index of this
+// thread's first set bit.  Contains three block barriers; the list is
+// complete when it returns.
+__device__ __forceinline__ uint32_t block_list(uint32_t mask, uint16_t* list, uint32_t* wl,
+                                               uint32_t* first) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t c = __popc(mask);
+    uint32_t excl = 0, wtot = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const uint64_t bal = __ballot((c >> b) & 1u);
+        excl += lane_rank(bal) << b;
+        wtot += static_cast<uint32_t>(__popcll(bal)) << b;
+    }
+    __syncthreads();   // earlier readers of wl and list are done
+    if (lane == 0) wl[wave] = wtot;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t v = wl[w];
+        before += w < wave ? v : 0u;
+        total += v;
+    }
+    uint32_t r = before + excl;
+    *first = r;
+    for (uint32_t m = mask; m; m &= m - 1u) list[r++] = uint16_t(threadIdx.x * 32u + (__ffs(m) - 1));
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(total);
+}
+
+// A list entry is a 13-bit tile offset; a kernel may tag it with a 2-bit
+// flag in bits 14-15 once it has read the offset.
+__device__ __forceinline__ void tag(uint16_t* list, uint32_t j, uint32_t f) {
+    list[j] = uint16_t((list[j] & 0x1FFFu) | (f << 14));
+}
+
+// The bits of `mask` whose list entries (in slot order from `first`) carry
+// flag value v.
+__device__ __forceinline__ uint32_t flagged(uint32_t mask, uint32_t first, const uint16_t* list,
+                                            uint32_t v) {
+    uint32_t out = 0, r = first;
+    for (uint32_t m = mask; m; m &= m - 1u, ++r)
+        if ((list[r] >> 14) == v) out |= m & (0u - m);
+    return out;
+}
+
+__device__ __forceinline__ bool grown(int32_t ready, uint32_t step) {
+    return int32_t(uint32_t(ready) - step) <= 0;
+}
+
 // ------------------------------------------------------------------ K1
 __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
-    __shared__ uint32_t lds[kBlock / 64];
-    const int64_t g = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    const int s = g < a.cap_s ? 0 : 1;
-    const int64_t i = s ? g - a.cap_s : g;
-    const int64_t cap = s ? a.cap_w : a.cap_s;
+    __shared__ uint16_t list[kTile];
+    __shared__ uint32_t wl[kWaves];
+    __shared__ uint32_t lds[kWaves];
+    const TileRef t = tile_of(a);
+    const int s = t.s;
+    const Species sp = a.sp[s];
+    const uint32_t mask = a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x];
+    uint32_t first;
+    const uint32_t n = block_list(mask, list, wl, &first);
     const uint64_t skey = stream_key(a.seed, a.step);
-    uint32_t live_s = 0, live_w = 0;
-    if (i < cap && a.sp[s].alive[i] != 0) {
-        (s ? live_w : live_s) = 1;
-        const uint32_t d = draw(skey, uint32_t(i), s ? kWolfMove : kSheepMove) >> 29;
-        const int32_t dx = int32_t((kDxPacked >> (2 * d)) & 3u) - 1;
-        const int32_t dy = int32_t((kDyPacked >> (2 * d)) & 3u) - 1;
-        const int32_t x = wrap_step(a.sp[s].x[i], dx, a.W);
-        const int32_t y = wrap_step(a.sp[s].y[i], dy, a.H);
-        a.sp[s].x[i] = x;
-        a.sp[s].y[i] = y;
-        a.sp[s].e[i] -= 1;
-        const int64_t c = cell_of(x, y, a.W, a.H);
-        if (c < 0) {
-        } else if (a.multi) {
-            // push slot i onto the list of its cell; the list ends at all-ones
-            if (s == 0 && a.grass[c] == 0)
-                atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c),
-                          (unsigned long long)agent_key(skey, i, kSheepGrassKey));
-            uint64_t* head = (s ? a.wclaim : a.sclaim) + c;
-            const uint64_t prev = atomicExch(reinterpret_cast<unsigned long long*>(head),
-                                             (unsigned long long)i);
-            a.blist[s][i] = int32_t(prev);   // all-ones -> -1
-        } else if (s == 0) {
-            if (a.grass[c] == 0)
-                atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c),
-                          (unsigned long long)agent_key(skey, i, kSheepGrassKey));
-            atomicMin(reinterpret_cast<unsigned long long*>(a.sclaim + c),
-                      (unsigned long long)agent_key(skey, i, kSheepPreyKey));
-        } else {
-            atomicMin(reinterpret_cast<unsigned long long*>(a.wclaim + c),
-                      (unsigned long long)agent_key(skey, i, kWolfEatKey));
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+        int64_t i[kInFlight], c[kInFlight];
+        int32_t x[kInFlight], y[kInFlight];
+        bool on[kInFlight];
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            on[q] = j < n;
+            i[q] = t.base + (on[q] ? list[j] : 0);
+            if (on[q]) {
+                x[q] = sp.x[i[q]];
+                y[q] = sp.y[i[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q]) continue;
+            const uint32_t d = draw(skey, uint32_t(i[q]), s ? kWolfMove : kSheepMove) >> 29;
+            x[q] = wrap_step(x[q], int32_t((kDxPacked >> (2 * d)) & 3u) - 1, a.W);
+            y[q] = wrap_step(y[q], int32_t((kDyPacked >> (2 * d)) & 3u) - 1, a.H);
+            sp.x[i[q]] = x[q];
+            sp.y[i[q]] = y[q];
+            sp.e[i[q]] -= 1;
+            c[q] = cell_of(x[q], y[q], a.W, a.H);
+        }
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q] || c[q] < 0) continue;
+            if (a.multi) {
+                // push slot i onto the list of its cell; the list ends at all-ones
+                if (s == 0 && grown(a.ready[c[q]], a.step))
+                    atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c[q]),
+                              (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
+                uint64_t* head = (s ? a.wclaim : a.sclaim) + c[q];
+                const uint64_t prev = atomicExch(reinterpret_cast<unsigned long long*>(head),
+                                                 (unsigned long long)i[q]);
+                a.blist[s][i[q]] = int32_t(prev);   // all-ones -> -1
+            } else if (s == 0) {
+                if (grown(a.ready[c[q]], a.step))
+                    atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c[q]),
+                              (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
+                atomicMin(reinterpret_cast<unsigned long long*>(a.sclaim + c[q]),
+                          (unsigned long long)agent_key(skey, i[q], kSheepPreyKey));
+            } else {
+                atomicMin(reinterpret_cast<unsigned long long*>(a.wclaim + c[q]),
+                          (unsigned long long)agent_key(skey, i[q], kWolfEatKey));
+            }
         }
     }
-    if (a.stats) {
-        block_add(live_s, a.acc, kLiveS, lds);
-        block_add(live_w, a.acc, kLiveW, lds);
-    }
+    if (a.stats) block_add(__popc(mask), a.acc, s ? kLiveW : kLiveS, lds);
 }
 
 // K1b (multi_prey): wolf j of cell c takes rank r among the wolves of c (eat
@@ -236,75 +353,76 @@ __global__ __launch_bounds__(kBlock) void k_prey_match(StepArgs a) {
     }
 }
 
-// Maps workgroup t to (species, first tile of that species' scan chain).
-__device__ __forceinline__ void species_tile(const StepArgs& a, uint32_t& tile, int& s,
-                                             uint32_t& seg_first) {
-    tile = blockIdx.x;
-    s = tile < a.tiles[0] ? 0 : 1;
-    seg_first = s ? a.tiles[0] : 0u;
-}
-
 // ------------------------------------------------------------------ K2
-__global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
+    __shared__ uint16_t list[kTile];
+    __shared__ uint32_t wl[kWaves];
     __shared__ uint32_t lds[kWaves + 1];
-    uint32_t tile, seg_first;
-    int s;
-    species_tile(a, tile, s, seg_first);
-    const uint32_t epoch = read_epoch(a.epoch);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t cap = s ? a.cap_w : a.cap_s;
-    const int64_t base = int64_t(tile - seg_first) * kTile + int64_t(wave) * kItems * 64 + lane;
-    const uint64_t skey = stream_key(a.seed, a.step);
+    const TileRef t = tile_of(a);
+    const int s = t.s;
     const Species sp = a.sp[s];
+    const uint32_t epoch = read_epoch(a.epoch);
+    const uint32_t mask = a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x];
+    uint32_t first;
+    const uint32_t n = block_list(mask, list, wl, &first);
+    const uint64_t skey = stream_key(a.seed, a.step);
     uint32_t grass_eaten = 0, sheep_eaten = 0;
-    bool f[kItems];
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+        int64_t i[kInFlight], c[kInFlight];
+        int32_t e[kInFlight];
+        bool on[kInFlight], eaten[kInFlight];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t i = base + k * 64;
-        f[k] = false;
-        if (i >= cap || sp.alive[i] == 0) continue;
-        const int64_t c = cell_of(sp.x[i], sp.y[i], a.W, a.H);
-        int32_t e = sp.e[i];
-        if (c < 0) {
-            f[k] = e > 0 && draw(skey, uint32_t(i), s ? kWolfBreed : kSheepBreed) < (s ? a.T_w : a.T_s);
-            continue;
+        for (int q = 0; q < kInFlight; ++q) {
+            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            on[q] = j < n;
+            i[q] = t.base + (on[q] ? list[j] : 0);
+            c[q] = on[q] ? cell_of(sp.x[i[q]], sp.y[i[q]], a.W, a.H) : -1;
+            e[q] = on[q] ? sp.e[i[q]] : 0;
+            eaten[q] = s == 0 && a.multi && on[q] && sp.alive[i[q]] == 2;
         }
-        if (s == 0) {
-            if (a.gclaim[c] == agent_key(skey, i, kSheepGrassKey)) {
-                e += a.gain_s;
-                sp.e[i] = e;
-                a.grass[c] = a.R;
-                ++grass_eaten;
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q] || c[q] < 0) continue;
+            if (s == 0) {
+                if (a.gclaim[c[q]] == agent_key(skey, i[q], kSheepGrassKey)) {
+                    e[q] += a.gain_s;
+                    sp.e[i[q]] = e[q];
+                    a.ready[c[q]] = int32_t(a.step + uint32_t(a.R));
+                    ++grass_eaten;
+                }
+                if (!a.multi)
+                    eaten[q] = a.wclaim[c[q]] != kNoClaim &&
+                               a.sclaim[c[q]] == agent_key(skey, i[q], kSheepPreyKey);
+                if (eaten[q]) {
+                    if (!a.multi) sp.alive[i[q]] = 2;
+                    ++sheep_eaten;
+                }
+            } else if (!a.multi && a.sclaim[c[q]] != kNoClaim &&
+                       a.wclaim[c[q]] == agent_key(skey, i[q], kWolfEatKey)) {
+                // (multi_prey: K1b has already added the gain)
+                e[q] += a.gain_w;
+                sp.e[i[q]] = e[q];
             }
-            const bool eaten =
-                a.multi ? sp.alive[i] == 2
-                        : (a.wclaim[c] != kNoClaim &&
-                           a.sclaim[c] == agent_key(skey, i, kSheepPreyKey));
-            if (eaten) {
-                sp.alive[i] = 0;
-                ++sheep_eaten;
-                continue;
-            }
-            f[k] = e > 0 && draw(skey, uint32_t(i), kSheepBreed) < a.T_s;
-        } else {
-            // (multi_prey: K1b has already added the gain)
-            if (!a.multi && a.sclaim[c] != kNoClaim &&
-                a.wclaim[c] == agent_key(skey, i, kWolfEatKey)) {
-                e += a.gain_w;
-                sp.e[i] = e;
-            }
-            f[k] = e > 0 && draw(skey, uint32_t(i), kWolfBreed) < a.T_w;
+        }
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q]) continue;
+            const bool br = !eaten[q] && e[q] > 0 &&
+                            draw(skey, uint32_t(i[q]), s ? kWolfBreed : kSheepBreed) <
+                                (s ? a.T_w : a.T_s);
+            tag(list, j0 + uint32_t(q * kBlock) + threadIdx.x, br ? 1u : 0u);
         }
     }
-    uint32_t rank[kItems], total;
-    const uint32_t tile_excl =
-        rank_tile<kWaves, kItems>(f, rank, a.status + a.chain_off[s], a.status - 1,
-                                  tile - seg_first, a.tiles[s], epoch, lds, &total);
-#pragma unroll
-    for (int k = 0; k < kItems; ++k)
-        if (f[k]) a.blist[s][rank[k]] = int32_t(base + k * 64);
-    const uint32_t last = seg_first + a.tiles[s] - 1;
-    if (tile == last && threadIdx.x == 0) *a.d_nb[s] = int64_t(tile_excl) + total;
+    __syncthreads();
+    const uint32_t bm = flagged(mask, first, list, 1);
+    uint32_t r0, total;
+    const uint32_t tile_excl = rank_counts<kWaves>(__popc(bm), &r0, a.status + a.chain_off[s],
+                                                   a.status - 1, t.tile, a.tiles[s], epoch, lds,
+                                                   &total);
+    uint32_t r = tile_excl + r0;
+    for (uint32_t m = bm; m; m &= m - 1u)
+        a.blist[s][r++] = int32_t(t.base + threadIdx.x * 32u + (__ffs(m) - 1));
+    if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) *a.d_nb[s] = int64_t(tile_excl) + total;
     if (a.stats && s == 0) {
         block_add(grass_eaten, a.acc, kGrassEaten, lds);
         block_add(sheep_eaten, a.acc, kSheepEaten, lds);
@@ -312,52 +430,112 @@ __global__ __launch_bounds__(kWaves * 64) void k_eat_breeders(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ K3
-__global__ __launch_bounds__(kWaves * 64) void k_breed_die(StepArgs a) {
+__global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
+    __shared__ uint16_t list[kTile];
+    __shared__ uint32_t wl[kWaves];
     __shared__ uint32_t lds[kWaves + 1];
-    uint32_t tile, seg_first;
-    int s;
-    species_tile(a, tile, s, seg_first);
-    const uint32_t epoch = read_epoch(a.epoch);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t cap = s ? a.cap_w : a.cap_s;
-    const int64_t base = int64_t(tile - seg_first) * kTile + int64_t(wave) * kItems * 64 + lane;
+    const TileRef t = tile_of(a);
+    const int s = t.s;
     const Species sp = a.sp[s];
-    bool f[kItems], live[kItems];
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t i = base + k * 64;
-        const bool in = i < cap;
-        const int32_t al = in ? sp.alive[i] : 1;
-        f[k] = in && al == 0;
-        live[k] = in && al != 0;
+    const uint32_t epoch = read_epoch(a.epoch);
+    const int64_t cap = s ? a.cap_w : a.cap_s;
+    const int64_t wi = int64_t(t.tile) * kBlock + threadIdx.x;
+    const uint32_t mask = a.bits[s][wi];          // live at K1, eaten sheep included
+    uint32_t first;
+    const uint32_t n = block_list(mask, list, wl, &first);
+    // this workgroup's slice of the claim tables is re-armed for the next
+    // step (K2, the last reader, has finished): whole lines, streamed, which
+    // measured faster than each agent resetting the words it posted (scattered
+    // 8-byte stores, each a read-modify-write at the memory)
+    {
+        const int64_t words = 3 * a.G, per = (words + gridDim.x - 1) / gridDim.x;
+        const int64_t lo = int64_t(blockIdx.x) * per;
+        const int64_t hi = lo + per < words ? lo + per : words;
+        for (int64_t w = lo + threadIdx.x; w < hi; w += kBlock) a.gclaim[w] = kNoClaim;
     }
-    uint32_t rank[kItems], total;
-    const uint32_t tile_excl =
-        rank_tile<kWaves, kItems>(f, rank, a.status + a.chain_off[s], a.status - 1,
-                                  tile - seg_first, a.tiles[s], epoch, lds, &total);
-    const int64_t nb = *a.d_nb[s];
+    // eaten sheep become free slots, starving agents die
     uint32_t starved = 0;
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+        int64_t i[kInFlight];
+        int32_t al[kInFlight], e[kInFlight];
+        bool on[kInFlight];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        const int64_t i = base + k * 64;
-        if (f[k] && int64_t(rank[k]) < nb) {
-            const int32_t p = a.blist[s][rank[k]];
-            const int32_t ep = sp.e[p];
-            const int32_t ec = ep >> 1;
-            sp.x[i] = sp.x[p];
-            sp.y[i] = sp.y[p];
-            sp.e[i] = ec;
-            sp.e[p] = ep - ec;
-            sp.alive[i] = 1;
-        } else if (live[k] && sp.e[i] < 0) {
-            // a breeder's energy stays positive, so no slot read by a child dies here
-            sp.alive[i] = 0;
-            ++starved;
+        for (int q = 0; q < kInFlight; ++q) {
+            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            on[q] = j < n;
+            i[q] = t.base + (on[q] ? list[j] : 0);
+            al[q] = on[q] ? sp.alive[i[q]] : 0;
+            e[q] = on[q] ? sp.e[i[q]] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q]) continue;
+            uint32_t f = 0;
+            if (al[q] == 2) {
+                f = 1;                      // eaten: a free slot for this step's births
+                sp.alive[i[q]] = 0;
+            } else if (e[q] < 0) {
+                // a breeder's energy stays positive, so no slot read by a child dies here
+                f = 2;
+                sp.alive[i[q]] = 0;
+                ++starved;
+            }
+            tag(list, j0 + uint32_t(q * kBlock) + threadIdx.x, f);
         }
     }
-    const uint32_t last = seg_first + a.tiles[s] - 1;
+    __syncthreads();
+    const uint32_t eaten_m = flagged(mask, first, list, 1);
+    const uint32_t starved_m = flagged(mask, first, list, 2);
+    const int64_t lane0 = t.base + int64_t(threadIdx.x) * 32;
+    const uint32_t in_cap = lane0 >= cap ? 0u : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
+    const uint32_t free_m = ((~mask) & in_cap) | eaten_m;
+    uint32_t r0, total;
+    const uint32_t tile_excl = rank_counts<kWaves>(__popc(free_m), &r0, a.status + a.chain_off[s],
+                                                   a.status - 1, t.tile, a.tiles[s], epoch, lds,
+                                                   &total);
+    const int64_t nb = *a.d_nb[s];
+    const int64_t room = nb - int64_t(tile_excl);
+    const uint32_t births = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
+    // this lane's free slots of tile rank < births receive children
+    const uint32_t mine = births > r0 ? (births - r0 < 32u ? births - r0 : 32u) : 0u;
+    uint32_t born_m = 0;
+    {
+        uint32_t m = free_m;
+        for (uint32_t k = 0; k < mine && m; ++k, m &= m - 1u) born_m |= m & (0u - m);
+    }
+    a.bits[s][wi] = (mask & ~eaten_m & ~starved_m) | born_m;
+    // the children, spread over the block: list the free slots that receive one
+    uint32_t bfirst;
+    const uint32_t nborn = block_list(born_m, list, wl, &bfirst);
+    for (uint32_t j0 = 0; j0 < nborn; j0 += kInFlight * kBlock) {
+        int64_t ci[kInFlight], p[kInFlight];
+        int32_t px[kInFlight], py[kInFlight], pe[kInFlight];
+        bool on[kInFlight];
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            on[q] = j < nborn;
+            ci[q] = t.base + (on[q] ? list[j] : 0);
+            p[q] = on[q] ? a.blist[s][tile_excl + j] : 0;
+            if (on[q]) {
+                px[q] = sp.x[p[q]];
+                py[q] = sp.y[p[q]];
+                pe[q] = sp.e[p[q]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kInFlight; ++q) {
+            if (!on[q]) continue;
+            const int32_t ec = pe[q] >> 1;
+            sp.x[ci[q]] = px[q];
+            sp.y[ci[q]] = py[q];
+            sp.e[ci[q]] = ec;
+            sp.e[p[q]] = pe[q] - ec;
+            sp.alive[ci[q]] = 1;
+        }
+    }
     if (a.stats) {
-        if (tile == last && threadIdx.x == 0) {
+        if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
             const int64_t nfree = int64_t(tile_excl) + total;
             a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
         }
@@ -365,36 +543,63 @@ __global__ __launch_bounds__(kWaves * 64) void k_breed_die(StepArgs a) {
     }
 }
 
-// ------------------------------------------------------------------ K4
-// Workgroup 0 also folds the step's spread accumulators into its stats row
-// and clears them for the next step (the births columns are written directly
-// by the breed kernel).
-__global__ __launch_bounds__(kBlock) void k_regrow_rearm(int32_t* __restrict__ grass,
-                                                         uint64_t* __restrict__ claims, int64_t G,
-                                                         int do_regrow, int64_t* acc,
-                                                         int64_t* stats) {
-    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (stats && blockIdx.x == 0) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int col = wave; col < kAccCounters; col += kBlock / 64) {
-            int64_t v = 0;
-            for (int l = lane; l < kAccLanes; l += 64) {
-                v += acc[col * kAccLanes + l];
-                acc[col * kAccLanes + l] = 0;
-            }
+// ------------------------------------------------------------------ call edges
+// Start of a call: grass countdowns -> ready steps, live bitmasks from alive,
+// every claim word re-armed.  One thread per bitmask word (and cell).
+__global__ __launch_bounds__(kBlock) void k_call_begin(StepArgs a, int64_t G, int64_t words_s,
+                                                       int64_t words_w) {
+    const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (k < G) {
+        a.ready[k] = int32_t(a.step + uint32_t(a.ready[k]));
+        a.gclaim[k] = kNoClaim;
+        a.sclaim[k] = kNoClaim;
+        a.wclaim[k] = kNoClaim;
+    }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0 && col != kBirthsS && col != kBirthsW) stats[col] = v;
+    for (int s = 0; s < 2; ++s) {
+        const int64_t words = s ? words_w : words_s;
+        const int64_t cap = s ? a.cap_w : a.cap_s;
+        if (k >= words) continue;
+        const int32_t* al = a.sp[s].alive + k * 32;
+        uint32_t m = 0;
+        if (k * 32 + 32 <= cap && (reinterpret_cast<uintptr_t>(al) & 15) == 0) {
+            int4 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = reinterpret_cast<const int4*>(al)[q];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                m |= uint32_t(v[q].x != 0) << (4 * q) | uint32_t(v[q].y != 0) << (4 * q + 1) |
+                     uint32_t(v[q].z != 0) << (4 * q + 2) | uint32_t(v[q].w != 0) << (4 * q + 3);
+        } else {
+            for (int b = 0; b < 32 && k * 32 + b < cap; ++b) m |= uint32_t(al[b] != 0) << b;
         }
+        a.bits[s][k] = m;
     }
-    if (c >= G) return;
-    if (do_regrow) {
-        const int32_t g = grass[c];
-        if (g > 0) grass[c] = g - 1;
+}
+
+// End of a call: ready steps -> countdowns at step `end`.
+__global__ __launch_bounds__(kBlock) void k_call_end(int32_t* grass, int64_t G, uint32_t end) {
+    const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (c < G) {
+        const int32_t d = int32_t(uint32_t(grass[c]) - end);
+        grass[c] = d > 0 ? d : 0;
     }
-    claims[c] = kNoClaim;
-    claims[G + c] = kNoClaim;
-    claims[2 * G + c] = kNoClaim;
+}
+
+// Folds a step's spread accumulators into its stats row (the births columns
+// are written by K3) and clears them for the next step.
+__global__ __launch_bounds__(kBlock) void k_fold_stats(int64_t* acc, int64_t* stats) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int col = wave; col < kAccCounters; col += kBlock / 64) {
+        int64_t v = 0;
+        for (int l = lane; l < kAccLanes; l += 64) {
+            v += acc[col * kAccLanes + l];
+            acc[col * kAccLanes + l] = 0;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && col != kBirthsS && col != kBirthsW) stats[col] = v;
+    }
 }
 
 int check_params(const abm_predation_params* p) {
@@ -493,9 +698,12 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.seed = p->seed;
     a.cap_s = p->cap_s;
     a.cap_w = p->cap_w;
-    a.grass = s->grass;
+    a.ready = s->grass;
     a.sp[0] = species_of(s->sheep);
     a.sp[1] = species_of(s->wolves);
+    a.bits[0] = w.bits_a;
+    a.bits[1] = w.bits_b;
+    a.G = G;
     a.gclaim = s->claims;
     a.sclaim = s->claims + G;
     a.wclaim = s->claims + 2 * G;
@@ -510,14 +718,17 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.chain_off[0] = 0;
     a.chain_off[1] = static_cast<uint32_t>(chain_words(a.tiles[0]));
     a.multi = p->multi_prey;
+    a.step = s->step;
+    a.stats = nullptr;
 
-    const dim3 cell_grid(static_cast<uint32_t>(tiles_for(G, kBlock)));
-    const dim3 agent_grid(static_cast<uint32_t>(tiles_for(p->cap_s + p->cap_w, kBlock)));
-    const dim3 scan_grid(a.tiles[0] + a.tiles[1]);
-    // the claim tables and accumulators start the call empty whatever the
-    // caller did between calls
-    hipLaunchKernelGGL(k_regrow_rearm, cell_grid, dim3(kBlock), 0, st, s->grass, s->claims, G, 0,
-                       nullptr, nullptr);
+    const int64_t words_s = int64_t(a.tiles[0]) * kBlock, words_w = int64_t(a.tiles[1]) * kBlock;
+    int64_t edge = G > words_s ? G : words_s;
+    if (words_w > edge) edge = words_w;
+    const dim3 tile_grid(a.tiles[0] + a.tiles[1]);
+    // grass to ready steps, live bitmasks from alive, claim tables re-armed
+    // (whatever the caller did to the state between calls)
+    hipLaunchKernelGGL(k_call_begin, dim3(static_cast<uint32_t>(tiles_for(edge, kBlock))),
+                       dim3(kBlock), 0, st, a, G, words_s, words_w);
     hipLaunchKernelGGL(k_fill64, dim3(tiles_for(kAccWords, kBlock)), dim3(kBlock), 0, st, w.acc,
                        kAccWords, int64_t(0));
     if (s->stats)
@@ -526,19 +737,20 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     for (int32_t k = 0; k < n_steps; ++k) {
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
-        hipLaunchKernelGGL(k_move_claim, agent_grid, dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_move_claim, tile_grid, dim3(kBlock), 0, st, a);
         if (a.multi)
             hipLaunchKernelGGL(k_prey_match, dim3(static_cast<uint32_t>(tiles_for(p->cap_w, kBlock))),
                                dim3(kBlock), 0, st, a);
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
-        hipLaunchKernelGGL(k_eat_breeders, scan_grid, dim3(kWaves * 64), 0, st, a);
+        hipLaunchKernelGGL(k_eat_breeders, tile_grid, dim3(kBlock), 0, st, a);
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
-        hipLaunchKernelGGL(k_breed_die, scan_grid, dim3(kWaves * 64), 0, st, a);
-        hipLaunchKernelGGL(k_regrow_rearm, cell_grid, dim3(kBlock), 0, st, s->grass, s->claims, G,
-                           1, w.acc, a.stats);
+        hipLaunchKernelGGL(k_breed_die, tile_grid, dim3(kBlock), 0, st, a);
+        if (a.stats) hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, st, w.acc, a.stats);
     }
+    hipLaunchKernelGGL(k_call_end, dim3(static_cast<uint32_t>(tiles_for(G, kBlock))), dim3(kBlock),
+                       0, st, s->grass, G, s->step + uint32_t(n_steps));
     rc = launch_status("predation_step");
     if (rc == ABM_OK) s->step += uint32_t(n_steps);
     return rc;
