@@ -79,10 +79,9 @@ struct StepArgs {
     Species sp[2];        // 0 sheep, 1 wolves
     uint32_t* bits[2];    // live-slot bitmasks
     int64_t G;            // cells
-    uint64_t* gclaim;     // grass: lowest sheep key per grown cell (the three
-                          // tables are consecutive: gclaim, sclaim, wclaim)
-    uint64_t* sclaim;     // prey: lowest sheep key per cell
-    uint64_t* wclaim;     // eater: lowest wolf key per cell
+    uint64_t* claims;     // three words per cell c, at 3 c: grass (the lowest key
+                          // of a sheep on the grown cell), prey (lowest sheep
+                          // key), eater (lowest wolf key); together in one line
     int64_t* stats;       // this step's row of 8, or null
     int64_t* acc;         // kAccCounters x kAccLanes spread accumulators
     uint32_t step;
@@ -302,20 +301,20 @@ __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
             if (a.multi) {
                 // push slot i onto the list of its cell; the list ends at all-ones
                 if (s == 0 && grown(a.ready[c[q]], a.step))
-                    atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c[q]),
+                    atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q]),
                               (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
-                uint64_t* head = (s ? a.wclaim : a.sclaim) + c[q];
+                uint64_t* head = a.claims + 3 * c[q] + (s ? 2 : 1);
                 const uint64_t prev = atomicExch(reinterpret_cast<unsigned long long*>(head),
                                                  (unsigned long long)i[q]);
                 a.blist[s][i[q]] = int32_t(prev);   // all-ones -> -1
             } else if (s == 0) {
                 if (grown(a.ready[c[q]], a.step))
-                    atomicMin(reinterpret_cast<unsigned long long*>(a.gclaim + c[q]),
+                    atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q]),
                               (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
-                atomicMin(reinterpret_cast<unsigned long long*>(a.sclaim + c[q]),
+                atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q] + 1),
                           (unsigned long long)agent_key(skey, i[q], kSheepPreyKey));
             } else {
-                atomicMin(reinterpret_cast<unsigned long long*>(a.wclaim + c[q]),
+                atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q] + 2),
                           (unsigned long long)agent_key(skey, i[q], kWolfEatKey));
             }
         }
@@ -337,9 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_prey_match(StepArgs a) {
     const uint64_t skey = stream_key(a.seed, a.step);
     const uint64_t my_key = agent_key(skey, j, kWolfEatKey);
     uint32_t r = 0;
-    for (int32_t w = int32_t(a.wclaim[c]); w >= 0; w = a.blist[1][w])
+    for (int32_t w = int32_t(a.claims[3 * c + 2]); w >= 0; w = a.blist[1][w])
         r += agent_key(skey, w, kWolfEatKey) < my_key;
-    const int32_t first = int32_t(a.sclaim[c]);
+    const int32_t first = int32_t(a.claims[3 * c + 1]);
     for (int32_t q = first; q >= 0; q = a.blist[0][q]) {
         const uint64_t kq = agent_key(skey, q, kSheepPreyKey);
         uint32_t below = 0;
@@ -384,21 +383,21 @@ __global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
         for (int q = 0; q < kInFlight; ++q) {
             if (!on[q] || c[q] < 0) continue;
             if (s == 0) {
-                if (a.gclaim[c[q]] == agent_key(skey, i[q], kSheepGrassKey)) {
+                if (a.claims[3 * c[q]] == agent_key(skey, i[q], kSheepGrassKey)) {
                     e[q] += a.gain_s;
                     sp.e[i[q]] = e[q];
                     a.ready[c[q]] = int32_t(a.step + uint32_t(a.R));
                     ++grass_eaten;
                 }
                 if (!a.multi)
-                    eaten[q] = a.wclaim[c[q]] != kNoClaim &&
-                               a.sclaim[c[q]] == agent_key(skey, i[q], kSheepPreyKey);
+                    eaten[q] = a.claims[3 * c[q] + 2] != kNoClaim &&
+                               a.claims[3 * c[q] + 1] == agent_key(skey, i[q], kSheepPreyKey);
                 if (eaten[q]) {
                     if (!a.multi) sp.alive[i[q]] = 2;
                     ++sheep_eaten;
                 }
-            } else if (!a.multi && a.sclaim[c[q]] != kNoClaim &&
-                       a.wclaim[c[q]] == agent_key(skey, i[q], kWolfEatKey)) {
+            } else if (!a.multi && a.claims[3 * c[q] + 1] != kNoClaim &&
+                       a.claims[3 * c[q] + 2] == agent_key(skey, i[q], kWolfEatKey)) {
                 // (multi_prey: K1b has already added the gain)
                 e[q] += a.gain_w;
                 sp.e[i[q]] = e[q];
@@ -451,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
         const int64_t words = 3 * a.G, per = (words + gridDim.x - 1) / gridDim.x;
         const int64_t lo = int64_t(blockIdx.x) * per;
         const int64_t hi = lo + per < words ? lo + per : words;
-        for (int64_t w = lo + threadIdx.x; w < hi; w += kBlock) a.gclaim[w] = kNoClaim;
+        for (int64_t w = lo + threadIdx.x; w < hi; w += kBlock) a.claims[w] = kNoClaim;
     }
     // eaten sheep become free slots, starving agents die
     uint32_t starved = 0;
@@ -551,9 +550,9 @@ __global__ __launch_bounds__(kBlock) void k_call_begin(StepArgs a, int64_t G, in
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
     if (k < G) {
         a.ready[k] = int32_t(a.step + uint32_t(a.ready[k]));
-        a.gclaim[k] = kNoClaim;
-        a.sclaim[k] = kNoClaim;
-        a.wclaim[k] = kNoClaim;
+        a.claims[3 * k] = kNoClaim;
+        a.claims[3 * k + 1] = kNoClaim;
+        a.claims[3 * k + 2] = kNoClaim;
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -704,9 +703,7 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.bits[0] = w.bits_a;
     a.bits[1] = w.bits_b;
     a.G = G;
-    a.gclaim = s->claims;
-    a.sclaim = s->claims + G;
-    a.wclaim = s->claims + 2 * G;
+    a.claims = s->claims;
     a.status = w.status;
     a.acc = w.acc;
     a.blist[0] = w.list_a;
