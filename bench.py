@@ -438,7 +438,8 @@ def traffic_leg(abm, torch, n_roads=500, length=100, steps=1000):
             "ms": ms, "car_updates": cars, "car_updates_per_s": cars / (ms / 1e3)}
 
 
-def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18):
+def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18, depth=1,
+               budget=1 << 23):
     """Served form: Poisson arrivals (rate/s for `seconds`), grid side log-uniform
     in [32, 1024], steps log-uniform in [100, 5000], admitted by HBM footprint
     into the running batched launch; open-loop latency from scheduled arrival.
@@ -446,7 +447,11 @@ def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18):
     (side >= ~400) are each advanced by a team of team_size workgroups, and the
     scheduler gives such a model team_size times the step budget of a solo one.
     Under this load teams of 4 halve the p99 latency of teams of 1 and raise
-    throughput by a third; 8 is slightly faster with a longer tail, 16 too coarse."""
+    throughput by a third; 8 is slightly faster with a longer tail, 16 too coarse.
+    depth = chunks in flight: 2 plans and submits the next chunk while one
+    runs; measured, the device was already busy 99.4 % of the time with 1, so
+    2 left the rate unchanged and raised the median latency (a new request
+    then waits behind two chunks)."""
     from paper_2508_16508_amd import serve as S
     from paper_2508_16508_amd import workloads as W
     trace = W.served_trace(0, rate=rate, duration_s=seconds)
@@ -455,7 +460,7 @@ def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18):
     runner = S.GpuRunner(cells, sheep, wolves,
                          max_model_cap=max(max(q.cap_s, q.cap_w) for q in reqs),
                          team_size=team_size, team_min_size=team_min_size)
-    sch = S.Scheduler(runner, cells, sheep, wolves,
+    sch = S.Scheduler(runner, cells, sheep, wolves, slot_step_budget=budget, depth=depth,
                       log=lambda m: print("served:", m, file=sys.stderr, flush=True))
     rep = sch.serve(reqs)
     out = rep.summary()
@@ -465,6 +470,10 @@ def served_leg(seconds, rate=200.0, team_size=4, team_min_size=1 << 18):
                        "sheep = cells/10, wolves = cells/40, capacities 4x")
     out["pools"] = {"cells": cells, "sheep_slots": sheep, "wolf_slots": wolves}
     out["teams"] = {"team_size": team_size, "team_min_size": team_min_size}
+    out["chunks_in_flight"], out["slot_step_budget"] = depth, budget
+    # every request completes, so the work is fixed by the trace: the served
+    # rate cannot exceed the work over the trace's duration
+    out["offered_agent_updates_per_s"] = out["agent_updates"] / seconds
     return out
 
 

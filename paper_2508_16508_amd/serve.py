@@ -19,6 +19,7 @@ from __future__ import annotations
 import bisect
 import ctypes as C
 import time
+from collections import deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -111,6 +112,7 @@ class Report:
     end_s: float = 0.0
     chunks: int = 0
     max_active: int = 0
+    device_busy_s: float = None   # device time of the chunks, when the runner measures it
 
     def summary(self) -> dict:
         lat = np.array([c[1] for c in self.completed]) if self.completed else np.zeros(1)
@@ -122,19 +124,34 @@ class Report:
                 "p50_latency_s": float(np.percentile(lat, 50)),
                 "p99_latency_s": float(np.percentile(lat, 99)),
                 "mean_queue_s": float(que.mean()), "chunks": self.chunks,
-                "max_active": self.max_active}
+                "max_active": self.max_active,
+                "device_idle_fraction": (None if self.device_busy_s is None
+                                         else max(0.0, 1.0 - self.device_busy_s / span))}
 
 
 class Scheduler:
-    """Continuous batching over pooled device state.
+    """Continuous batching over pooled device state, pipelined two chunks deep.
 
-    runner: object with init(models) -> None, run(models) -> list of (step,
-    updates) per model after the chunk, and finish(model) hooks; clock: a
-    callable returning seconds since the start of the trace."""
+    runner: object with submit(models, targets, admitted) -> ticket (enqueues,
+    without waiting, the initial state of `admitted` and one chunk advancing
+    each model to its target step), collect(ticket) -> list of (step, updates
+    made in that chunk) per model (waits for that chunk), finish(model) (the
+    model's last chunk has been submitted; its state ranges are then reused
+    by later chunks) and optionally workgroups_for(model); clock: a callable
+    returning seconds since the start of the trace.
+
+    A chunk advances every model to exactly its target, so the host knows
+    which models a chunk completes as soon as it submits it: it frees their
+    ranges, admits waiting requests into them and submits the next chunk while
+    the previous one still runs on the device (the device orders the next
+    chunk's initial states after it).  It then waits for the older chunk only,
+    so the device always has the next chunk queued while the host plans."""
 
     def __init__(self, runner, cell_capacity, sheep_capacity, wolf_capacity, max_active=4096,
-                 slot_step_budget=1 << 23, clock=None, sleep=None, log=None, log_every_s=5.0):
+                 slot_step_budget=1 << 23, clock=None, sleep=None, log=None, log_every_s=5.0,
+                 depth=2):
         self.runner = runner
+        self.depth = depth          # chunks in flight (1: wait for each chunk before the next)
         self.cells = RangeAllocator(cell_capacity)
         self.sheep = RangeAllocator(sheep_capacity)
         self.wolves = RangeAllocator(wolf_capacity)
@@ -165,6 +182,11 @@ class Scheduler:
             return None
         return Running(req, c, s, w, now)
 
+    def _release(self, r: Running):
+        self.cells.free(r.cell_off, r.req.cells)
+        self.sheep.free(r.sheep_off, r.req.cap_s)
+        self.wolves.free(r.wolf_off, r.req.cap_w)
+
     def chunk_target(self, r: Running) -> int:
         """Steps this model may advance in the next chunk: a budget of slot-steps
         per workgroup, split by the model's slot count, so small models run many
@@ -181,20 +203,20 @@ class Scheduler:
             if not self.fits(q):
                 raise ValueError(f"request {q.rid} can never fit the pools")
         waiting: list = []
-        active: list = []
+        active: list = []          # models with steps still to submit
+        inflight = deque()         # (ticket, models of the chunk, models it completes)
         rep = Report(start_s=self.clock())
         nxt = 0
         next_log = rep.start_s + self.log_every_s
-        while nxt < len(pending) or waiting or active:
+        while nxt < len(pending) or waiting or active or inflight:
             now = self.clock()
             while nxt < len(pending) and pending[nxt].arrival_s <= now:
                 waiting.append(pending[nxt])
                 nxt += 1
-            if not active and not waiting:
+            if not active and not waiting and not inflight:
                 self.sleep(max(0.0, pending[nxt].arrival_s - now))
                 continue
-            admitted = []
-            still = []
+            admitted, still = [], []
             for q in waiting:   # FIFO; a request that does not fit waits
                 r = self._admit(q, now) if len(active) + len(admitted) < self.max_active else None
                 if r is None:
@@ -202,35 +224,40 @@ class Scheduler:
                 else:
                     admitted.append(r)
             waiting = still
-            if admitted:
-                self.runner.init(admitted)
-                active.extend(admitted)
-            if not active:
-                # nothing fits until something retires; cannot happen with no active models
-                raise RuntimeError("pools too small for the waiting requests")
-            targets = [self.chunk_target(r) for r in active]
-            done_state = self.runner.run(active, targets)
-            rep.chunks += 1
-            rep.max_active = max(rep.max_active, len(active))
-            now = self.clock()
-            keep = []
-            for r, (step, updates) in zip(active, done_state):
-                r.step, r.updates = step, updates
-                if r.step >= r.req.steps:
+            active.extend(admitted)
+            if active and len(inflight) < self.depth:
+                targets = [self.chunk_target(r) for r in active]
+                ticket = self.runner.submit(active, targets, admitted)
+                rep.chunks += 1
+                rep.max_active = max(rep.max_active, len(active))
+                done, keep = [], []
+                for r, t in zip(active, targets):
+                    r.step = t
+                    (done if t >= r.req.steps else keep).append(r)
+                for r in done:
                     self.runner.finish(r)
-                    rep.completed.append((r.req.rid, now - r.req.arrival_s,
-                                          r.admit_s - r.req.arrival_s, r.updates))
-                    self.cells.free(r.cell_off, r.req.cells)
-                    self.sheep.free(r.sheep_off, r.req.cap_s)
-                    self.wolves.free(r.wolf_off, r.req.cap_w)
-                else:
-                    keep.append(r)
-            active = keep
+                    self._release(r)
+                inflight.append((ticket, list(active), done))
+                active = keep
+                if len(inflight) < self.depth and (active or waiting):
+                    continue       # plan the next chunk while this one runs
+            elif not inflight:
+                # nothing fits until something retires; cannot happen with nothing in flight
+                raise RuntimeError("pools too small for the waiting requests")
+            ticket, models, done = inflight.popleft()
+            results = self.runner.collect(ticket)
+            now = self.clock()
+            for r, (step, updates) in zip(models, results):
+                r.updates += updates
+            for r in done:
+                rep.completed.append((r.req.rid, now - r.req.arrival_s,
+                                      r.admit_s - r.req.arrival_s, r.updates))
             if self.log and now >= next_log:
                 next_log = now + self.log_every_s
                 self.log(f"t={now:7.2f}s arrived={nxt} waiting={len(waiting)} "
                          f"active={len(active)} done={len(rep.completed)} chunks={rep.chunks}")
         rep.end_s = self.clock()
+        rep.device_busy_s = getattr(self.runner, "busy_s", None)
         return rep
 
 
@@ -272,6 +299,15 @@ class GpuRunner:
         self.results = {}
         self.device = device
         self.workspace_error = 0
+        # pinned host staging, one set per chunk in flight
+        pin = lambda n, dt=torch.uint8: [torch.empty(n, dtype=dt, pin_memory=True) for _ in range(2)]
+        self.h_desc = pin(max_active * self.desc_size)
+        self.h_init = pin(max_active * self.desc_size)
+        self.h_out = pin(max_active * self.desc_size)
+        self.h_order = pin(max_active, torch.int32)
+        self.h_err = pin(8)
+        self._k = 0
+        self.busy_s = 0.0      # device time of the chunks' batched launches
 
     def _team_model(self, r) -> bool:
         return self.team_size > 1 and r.req.cells + r.req.cap_s + r.req.cap_w >= self.team_min_size
@@ -280,7 +316,10 @@ class GpuRunner:
         """Workgroups that will advance model r (a team, or one)."""
         return self.team_size if self._team_model(r) else 1
 
-    def _descs(self, models, targets):
+    def _descs(self, models, targets, zero=False):
+        """Descriptors for a chunk: each model at its (planned) step, advancing
+        to its target; updates start at 0, so the readback holds the chunk's
+        own count.  zero: step 0, for the initial state."""
         abm = self.abm
         arr = (abm.ModelDesc * max(1, len(models)))()
         for i, r in enumerate(models):
@@ -290,8 +329,8 @@ class GpuRunner:
             d.T_s, d.T_w, d.seed = T_SHEEP, T_WOLF, q.seed & 0xFFFFFFFF
             d.cap_s, d.cap_w, d.n_s0, d.n_w0 = q.cap_s, q.cap_w, q.n_s0, q.n_w0
             d.cell_off, d.sheep_off, d.wolf_off = r.cell_off, r.sheep_off, r.wolf_off
-            d.step, d.steps_target = r.step, targets[i]
-            d.updates = r.updates
+            d.step, d.steps_target = (0, 0) if zero else (r.step, targets[i])
+            d.updates = 0
         return arr
 
     def _batch(self, desc_tensor, n):
@@ -300,40 +339,71 @@ class GpuRunner:
         return abm.Batch(n, self.max_cap, desc_tensor.data_ptr(), self.ready.data_ptr(),
                          self.claims.data_ptr(), sp(self.sheep), sp(self.wolves))
 
-    def _upload(self, dst, arr, n):
+    def _stage(self, host, arr, n):
+        """Copies the first n descriptors of arr into the pinned host buffer."""
         raw = np.frombuffer(bytes(arr), dtype=np.uint8)[: n * self.desc_size]
-        dst[: n * self.desc_size].copy_(self.torch.from_numpy(raw.copy()), non_blocking=False)
+        host.numpy()[: n * self.desc_size] = raw
+        return host[: n * self.desc_size]
 
-    def init(self, models):
-        abm = self.abm
-        self._upload(self.init_desc, self._descs(models, [0] * len(models)), len(models))
-        b = self._batch(self.init_desc, len(models))
-        abm._check(abm.lib().abm_predation_batched_init(C.byref(b), abm._stream()))
-
-    def run(self, models, targets):
+    def submit(self, models, targets, admitted):
+        """Enqueues, without waiting: the initial state of the admitted models,
+        one chunk advancing every model to its target step, and the readback
+        of the descriptors and the error word.  Host buffers alternate between
+        the two chunks in flight; the device buffers are reused in stream order
+        (a chunk's uploads run after the previous chunk and its readback)."""
         abm, torch = self.abm, self.torch
+        slot = self._k % 2
+        self._k += 1
+        stream = torch.cuda.current_stream()
+        if admitted:
+            na = len(admitted)
+            h = self._stage(self.h_init[slot], self._descs(admitted, [0] * na, zero=True), na)
+            self.init_desc[: h.numel()].copy_(h, non_blocking=True)
+            b = self._batch(self.init_desc, na)
+            abm._check(abm.lib().abm_predation_batched_init(C.byref(b), abm._stream()))
         n = len(models)
-        self._upload(self.desc, self._descs(models, targets), n)
+        h = self._stage(self.h_desc[slot], self._descs(models, targets), n)
+        self.desc[: h.numel()].copy_(h, non_blocking=True)
         size = [r.req.cells + r.req.cap_s + r.req.cap_w for r in models]
-        order = np.argsort(-np.asarray(size), kind="stable").astype(np.int32)
-        self.order[:n].copy_(torch.from_numpy(order))
+        self.h_order[slot].numpy()[:n] = np.argsort(-np.asarray(size), kind="stable")
+        self.order[:n].copy_(self.h_order[slot][:n], non_blocking=True)
         b = self._batch(self.desc, n)
         n_team = sum(1 for r in models if self._team_model(r))
         t = abm.Tuning(self.block_threads, self.workgroups, self.items, self.team_size, n_team, 0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         abm._check(abm.lib().abm_predation_run_batched(C.byref(b), abm._p(self.order), 1 << 30,
                                                        C.byref(t), abm._p(self.ws),
                                                        self.ws.numel(), abm._stream()))
-        raw = self.desc[: n * self.desc_size].cpu().numpy().tobytes()   # synchronises
-        out = (abm.ModelDesc * n).from_buffer_copy(raw)
+        e1.record(stream)
+        self.h_out[slot][: n * self.desc_size].copy_(self.desc[: n * self.desc_size],
+                                                     non_blocking=True)
+        self.h_err[slot].copy_(self.ws[248:256], non_blocking=True)
+        done = torch.cuda.Event()
+        done.record(stream)
+        return (slot, n, e0, e1, done)
+
+    def collect(self, ticket):
+        """Waits for a submitted chunk: (step, updates made in the chunk) per model."""
+        abm = self.abm
+        slot, n, e0, e1, done = ticket
+        done.synchronize()
+        self.busy_s += e0.elapsed_time(e1) / 1e3
         # the error word is sticky: non-zero once any team barrier or bounded
         # wait of this workspace has given up, which leaves the states invalid
-        self.workspace_error = abm.workspace_error(self.ws)
+        self.workspace_error = int(self.h_err[slot].view(self.torch.int64)[0].item())
         if self.workspace_error:
             raise RuntimeError("batched kernel: a team barrier gave up (workspace error word "
                                "set); the served states are not valid")
+        raw = self.h_out[slot][: n * self.desc_size].numpy().tobytes()
+        out = (abm.ModelDesc * n).from_buffer_copy(raw)
         return [(d.step, d.updates) for d in out]
 
     def finish(self, r: Running):
+        """The model's last chunk is submitted.  With keep_results, its final
+        state is read back now (waiting for that chunk), before a later chunk
+        can reuse its ranges."""
         if not self.keep_results:
             return
         abm, torch = self.abm, self.torch
@@ -341,7 +411,8 @@ class GpuRunner:
         # a one-model view whose arrays start at this model's ranges
         d = self._descs([r], [r.step])
         d[0].cell_off = d[0].sheep_off = d[0].wolf_off = 0
-        self._upload(self.init_desc, d, 1)
+        torch.cuda.synchronize()
+        self.init_desc[: self.desc_size].copy_(self._stage(self.h_init[0], d, 1))
         cd = torch.zeros(q.cells, dtype=torch.int32, device=self.device)
         sp = lambda dd, o: abm.SpeciesPtrs(*(dd[k][o:].data_ptr() for k in ("x", "y", "e", "alive")))
         b = abm.Batch(1, self.max_cap, self.init_desc.data_ptr(), self.ready[r.cell_off:].data_ptr(),
@@ -352,7 +423,15 @@ class GpuRunner:
                  for k, v in self.sheep.items()}
         wolves = {k: v[r.wolf_off: r.wolf_off + q.cap_w].cpu().numpy()
                   for k, v in self.wolves.items()}
-        self.results[q.rid] = (cd.cpu().numpy(), sheep, wolves, r.updates)
+        torch.cuda.synchronize()
+        # the update count is complete once the scheduler has collected the chunk
+        self.results[q.rid] = [cd.cpu().numpy(), sheep, wolves, r]
+
+    def result(self, rid):
+        """(grass countdowns, sheep, wolves, agent updates) of a finished model
+        (keep_results), after the run."""
+        cd, sheep, wolves, r = self.results[rid]
+        return cd, sheep, wolves, r.updates
 
 
 def requests_from_trace(trace) -> list:

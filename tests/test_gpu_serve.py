@@ -34,7 +34,7 @@ def test_each_result_same_alone_and_in_the_mix(abm, orc, team_size):
                             n_s0=q.n_s0, n_w0=q.n_w0)
         St = orc.predation_init(P)
         st = orc.predation_run(P, St, q.steps)
-        grass, sheep, wolves, updates = runner.results[q.rid]
+        grass, sheep, wolves, updates = runner.result(q.rid)
         assert np.array_equal(grass, St.grass), q.rid
         for name, got, exp in (("sheep", sheep, St.sheep), ("wolves", wolves, St.wolves)):
             for f in ("x", "y", "e", "alive"):
@@ -82,7 +82,7 @@ def test_stratified_sample_of_the_served_trace(abm, orc):
                             cap_w=q.cap_w, n_s0=q.n_s0, n_w0=q.n_w0)
         St = orc.predation_init(P)
         st = orc.predation_run(P, St, q.steps)
-        grass, sheep_g, wolves_g, updates = runner.results[q.rid]
+        grass, sheep_g, wolves_g, updates = runner.result(q.rid)
         assert np.array_equal(grass, St.grass), q.rid
         for name, got, exp in (("sheep", sheep_g, St.sheep), ("wolves", wolves_g, St.wolves)):
             for f in ("x", "y", "e", "alive"):

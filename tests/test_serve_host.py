@@ -32,6 +32,7 @@ class FakeRunner:
         self.inited = []
         self.finished = []
         self.live_ranges = {}
+        self.submitted = self.collected = 0
 
     def init(self, models):
         for r in models:
@@ -42,10 +43,19 @@ class FakeRunner:
                 self.live_ranges[(name, r.req.rid)] = (off, n, r.req.rid)
             self.inited.append(r.req.rid)
 
-    def run(self, models, targets):
+    def submit(self, models, targets, admitted):
+        self.init(admitted)
         work = max((t - r.step) * (r.req.cap_s + r.req.cap_w) for r, t in zip(models, targets))
         self.clock.t += 1e-3 + work * 1e-9
-        return [(t, r.updates + (t - r.step) * 10) for r, t in zip(models, targets)]
+        self.submitted += 1
+        self.max_in_flight = max(getattr(self, "max_in_flight", 0),
+                                 self.submitted - self.collected)
+        return [(t, (t - r.step) * 10) for r, t in zip(models, targets)]
+
+    def collect(self, ticket):
+        self.collected += 1
+        assert self.submitted - self.collected <= 1   # at most two chunks in flight
+        return ticket
 
     def finish(self, r):
         self.finished.append(r.req.rid)
@@ -88,6 +98,7 @@ def test_every_request_completes_once_with_its_steps():
         assert upd == reqs[rid].steps * 10
     assert not run.live_ranges
     assert sch.cells.free_total == 50_000_000
+    assert run.max_in_flight == 2     # the next chunk is submitted before the last is collected
 
 
 def test_admission_waits_for_footprint():
@@ -139,3 +150,14 @@ def test_team_models_get_the_budget_of_every_member():
     rb, rs = Running(big, 0, 0, 0, 0.0), Running(small, 0, 0, 0, 0.0)
     assert sch.chunk_target(rb) == (4 << 22) // (big.cap_s + big.cap_w)
     assert sch.chunk_target(rs) == (1 << 22) // (small.cap_s + small.cap_w)
+
+
+def test_one_chunk_in_flight_waits_for_each_chunk():
+    clock = FakeClock()
+    run = FakeRunner(clock)
+    reqs = _trace(60, 2)
+    sch = Scheduler(run, 50_000_000, 20_000_000, 5_000_000, clock=clock, sleep=clock.sleep,
+                    depth=1)
+    rep = sch.serve(reqs)
+    assert sorted(c[0] for c in rep.completed) == list(range(60))
+    assert run.max_in_flight == 1
