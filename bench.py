@@ -35,6 +35,10 @@ N_SLOTS = 1 << 24
 N_ATTRS = 8
 
 
+LEGS = ("predation_small", "predation_large", "predation_large_multi_prey", "traffic", "lob",
+        "sort_select", "batched")
+
+
 def algorithmic_bytes(op, n, k):
     """Bytes the method must move per launch (see the roofline model)."""
     if op == "select_update":      # mask everywhere, k records read, k slots x 8 attrs written
@@ -486,7 +490,9 @@ def main():
     ap.add_argument("--cpu-seeds", type=int, default=3,
                     help="microbenchmark seeds timed in the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="run none of the legs below")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated legs to run after the microbenchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device 3 times (a transfer of known size "
                          "for scaling hardware byte counters)")
@@ -622,26 +628,36 @@ def main():
     }
     del sets, dst
     torch.cuda.empty_cache()
-    if not args.no_batched:
+    legs = [] if args.no_batched else args.legs.split(",")
+    unknown = set(legs) - set(LEGS)
+    if unknown:
+        raise SystemExit(f"unknown legs {sorted(unknown)}; known: {', '.join(LEGS)}")
+    if "predation_small" in legs:
         out["predation_small"] = predation_leg(
             abm, torch, dict(seed=0), 199,
             "64x64 torus, 400 sheep / 100 wolves in 4096 / 1024 slots, steps 1-199 after a "
             "warm-up step")
+    if "predation_large" in legs:
         out["predation_large"] = predation_leg(
             abm, torch, dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
                              n_w0=400_000, seed=0), 999,
             "2048x2048 torus, 1.6M sheep / 0.4M wolves in 2^24 / 2^22 slots, steps 1-999 "
             "after a warm-up step")
+    if "predation_large_multi_prey" in legs:
         out["predation_large_multi_prey"] = predation_leg(
             abm, torch, dict(W=2048, H=2048, cap_s=1 << 24, cap_w=1 << 22, n_s0=1_600_000,
                              n_w0=400_000, seed=0, multi_prey=1), 999,
             "2048x2048 torus as above with prey matched by rank within each cell (the r-th "
             "wolf of a cell eats its r-th sheep), steps 1-999 after a warm-up step")
+    if "traffic" in legs:
         out["traffic"] = traffic_leg(abm, torch)
+    if "lob" in legs:
         out["lob"] = lob_leg(abm, torch)
+    if "sort_select" in legs:
         out["sort_select"] = sort_select_leg(abm, torch, W)
+    if "batched" in legs:
         out["batched"] = batched_leg(abm, W, torch)
-        torch.cuda.empty_cache()
+    torch.cuda.empty_cache()
     if args.served_seconds > 0:
         out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)
         torch.cuda.empty_cache()
