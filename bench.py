@@ -253,18 +253,20 @@ def cpu_baseline_legs(oracle, W):
     return out
 
 
-def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps=20):
+def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps=20, lds=True,
+                max_side=256):
     """Batched form: 4096 uneven predation models (side 32-256, sheep = cells/10,
     wolves = cells/40, capacities 4x), `steps` steps as a graph of persistent
     launches of `chunk` steps each, against the one-model multi-launch path
     timed on a stratified subset of the same models (rates in agent updates/s;
-    both paths compute bit-identical states)."""
+    both paths compute bit-identical states).  max_side < 256 keeps only the
+    models of at most that side (a profiling subset, not the workload)."""
     from paper_2508_16508_amd.tune import autotune_batched
-    specs = W.batched_models(0, 4096)
+    specs = [sp for sp in W.batched_models(0, 4096) if sp.side <= max_side]
     params = [abm.predation_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s,
                                    cap_w=sp.cap_w, n_s0=sp.n_s0, n_w0=sp.n_w0) for sp in specs]
     def make(block, items):
-        b = abm.BatchedPredation(params, 1000, block_threads=block, items=items)
+        b = abm.BatchedPredation(params, 1000, block_threads=block, items=items, lds=lds)
         b.init()
         return b
 
@@ -272,7 +274,8 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     tuning = autotune_batched(make, "batched:4096 models side 32-256", steps=4, use_cache=False)
     torch.cuda.empty_cache()
     batch = abm.BatchedPredation(params, steps, block_threads=tuning["block_threads"],
-                                 items=tuning["items"])
+                                 items=tuning["items"], lds=lds)
+    lds_models, lds_cells = batch.lds_models(), batch.lds_cells()
     batch.init()
     batch.run(1)                           # warm-up (first step of every model)
     # the rest of the rollout, captured once by the library as a graph of
@@ -316,8 +319,9 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
     pupd = sum(int(st[:, 0].sum().item() + st[:, 1].sum().item()) for st in stats)
     rate_b = updates / (ms / 1e3)
     rate_p = pupd / (pms / 1e3)
+    subset = "" if max_side >= 256 else f" (only the {len(specs)} of side <= {max_side})"
     return {"workload": "4096 predation models, side uniform in [32, 256], sheep = cells/10, "
-                        "wolves = cells/40, capacities 4x, seeds base+m; "
+                        f"wolves = cells/40, capacities 4x, seeds base+m{subset}; "
                         f"{steps - 1} timed steps as one library-captured graph of {chunk}-step "
                         "persistent launches",
             "cells": cells, "agent_updates": updates, "ms": ms,
@@ -327,6 +331,8 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
                             f"{plain_steps} steps each, one-model multi-launch path",
             "batched_over_plain": rate_b / rate_p,
             "workspace_error": err,
+            "lds_claim_models": lds_models,
+            "lds_claim_max_cells": lds_cells,
             "tuning": {"block_threads": tuning["block_threads"], "items": tuning["items"],
                        "candidates_ms_per_4_steps": tuning["timings_ms"]}}
 
@@ -496,6 +502,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device 3 times (a transfer of known size "
                          "for scaling hardware byte counters)")
+    ap.add_argument("--batched-lds", choices=("on", "off"), default="on",
+                    help="keep the claim tables of the batch's smallest models in LDS")
+    ap.add_argument("--batched-max-side", type=int, default=256,
+                    help="profiling: keep only the batch's models of at most this side")
     ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served request trace (0 = skip)")
     ap.add_argument("--served-team-size", type=int, default=4,
@@ -656,7 +666,8 @@ def main():
     if "sort_select" in legs:
         out["sort_select"] = sort_select_leg(abm, torch, W)
     if "batched" in legs:
-        out["batched"] = batched_leg(abm, W, torch)
+        out["batched"] = batched_leg(abm, W, torch, lds=args.batched_lds == "on",
+                                     max_side=args.batched_max_side)
     torch.cuda.empty_cache()
     if args.served_seconds > 0:
         out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)

@@ -320,11 +320,14 @@ typedef struct abm_batch {        /* host struct of device pointers */
 typedef struct abm_tuning {
     int32_t block_threads;         /* threads per model workgroup (multiple of 64 in [256, 1024]); 0 = 512 */
     int32_t workgroups;            /* persistent workgroups; 0 = as many as are resident at once */
-    int32_t items;                 /* slots per thread per chunk: 1, 2, 4 or 8; 0 = 4 */
+    int32_t items;                 /* slots per thread per chunk: 1, 2 or 4; 0 = 4 */
     int32_t team_size;             /* workgroups per team (1..16); 0 or 1 = no teams */
     int32_t team_models;           /* the first team_models entries of order run in teams */
     int32_t team_workgroups;       /* workgroups formed into teams, a multiple of 8 * team_size;
                                       0 = enough for team_models teams (capped by residency) */
+    int32_t global_claims;         /* nonzero: every claim table in global memory; 0 = models
+                                      of one workgroup whose table fits keep it in LDS
+                                      (abm_batched_lds_cells) */
 } abm_tuning;
 
 /* Workspace for abm_predation_run_batched with at most n_workgroups
@@ -349,13 +352,25 @@ ABM_API int abm_predation_batched_init(const abm_batch* b, void* stream);
  * workgroups that split the model's slots into K contiguous ranges and meet
  * at three device-wide team barriers per step; the results are the same as
  * with one workgroup per model.  Teams need 8 K resident workgroups (else
- * ABM_E_INVALID).  The workspace must hold abm_batched_workspace_bytes(max_cap,
+ * ABM_E_INVALID).  Claim tables of small models are kept in LDS unless
+ * tune->global_claims is set (abm_batched_lds_cells).  The workspace must hold abm_batched_workspace_bytes(max_cap,
  * n) bytes, n being the number of workgroups launched: at most the resident
  * count (or tune->workgroups), which the caller can use as the bound.
  * Afterwards each descriptor's step, updates, live_s and live_w are current. */
 ABM_API int abm_predation_run_batched(const abm_batch* b, const int32_t* order, int32_t max_steps,
                                       const abm_tuning* tune, void* ws, size_t ws_bytes,
                                       void* stream);
+
+/* Largest W * H whose claim table (three uint64 per cell, 24 bytes) fits in
+ * the LDS that abm_predation_run_batched gives each workgroup at this launch
+ * shape on the current device: the CU's LDS shared among the workgroups
+ * resident at block_threads threads, less the kernel's own, so that no
+ * workgroup is displaced for it.  0 if no supported device is current or the
+ * shape is invalid.  Models advanced by one workgroup (not a team) whose table
+ * fits post, read and clear their claims in LDS; the results are the same as
+ * with the global table, whose cells of these models are left untouched
+ * (all-ones). */
+ABM_API int64_t abm_batched_lds_cells(int32_t block_threads, int32_t items);
 
 /* countdown[cell_off + c] = max(0, ready[cell_off + c] - step) for every model:
  * the grass array of the one-model state.  countdown: device int32[sum of W*H]. */

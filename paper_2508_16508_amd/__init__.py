@@ -32,6 +32,7 @@ EXPORTED = (
     "abm_resolve_conflicts_batched", "abm_traffic_init", "abm_traffic_step",
     "abm_sort_workspace_bytes", "abm_sort_agents", "abm_select_agents", "abm_lob_init",
     "abm_lob_step", "abm_predation_batched_graph", "abm_graph_replay", "abm_graph_destroy",
+    "abm_batched_lds_cells",
     "abm_select_update_noalloc",
 )
 
@@ -100,7 +101,7 @@ class Batch(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("workgroups", C.c_int32), ("items", C.c_int32),
                 ("team_size", C.c_int32), ("team_models", C.c_int32),
-                ("team_workgroups", C.c_int32)]
+                ("team_workgroups", C.c_int32), ("global_claims", C.c_int32)]
 
 
 _lib = None
@@ -133,6 +134,8 @@ def lib():
         L.abm_batched_workspace_bytes.argtypes = [i64, i32]
         L.abm_batched_workspace_bytes.restype = sz
         L.abm_predation_batched_init.argtypes = [C.POINTER(Batch), vp]
+        L.abm_batched_lds_cells.argtypes = [i32, i32]
+        L.abm_batched_lds_cells.restype = i64
         L.abm_predation_run_batched.argtypes = [C.POINTER(Batch), vp, i32, C.POINTER(Tuning), vp,
                                                 sz, vp]
         L.abm_predation_batched_grass.argtypes = [C.POINTER(Batch), vp, vp]
@@ -557,10 +560,11 @@ class BatchedPredation:
     (int or list).  Slot and cell ranges are packed in model order; the launch
     order is largest model first.  Models of at least team_min_size cells plus
     slots are each advanced by a team of team_size workgroups (team_size 1: no
-    teams)."""
+    teams).  With lds=True models of one workgroup whose claim table fits the
+    workgroup's LDS (lds_cells()) keep it there."""
 
     def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4,
-                 team_size=1, team_min_size=1 << 18):
+                 team_size=1, team_min_size=1 << 18, lds=True):
         self.params = list(models)
         if any(getattr(p, "multi_prey", 0) for p in self.params):
             raise ValueError("the batched form implements the one-prey rule only (multi_prey = 0)")
@@ -593,6 +597,7 @@ class BatchedPredation:
         self.order = torch.tensor(order or [0], dtype=torch.int32, device=device)
         self.size = size
         self.sorted_size = [size[m] for m in order]
+        self.lds = lds
         self.block_threads = block_threads
         self.items = items
         self.team_size = team_size
@@ -615,6 +620,18 @@ class BatchedPredation:
         b = self._batch()
         _check(lib().abm_predation_batched_init(C.byref(b), _stream(stream)))
 
+    def lds_cells(self, block_threads=None, items=None) -> int:
+        """Largest W * H whose claims stay in LDS at this launch shape (0: none)."""
+        if not self.lds:
+            return 0
+        return int(lib().abm_batched_lds_cells(block_threads or self.block_threads,
+                                               items or self.items))
+
+    def lds_models(self, block_threads=None, items=None) -> int:
+        """Models that keep their claims in LDS at this launch shape (no teams)."""
+        lim = self.lds_cells(block_threads, items)
+        return sum(1 for p in self.params if p.W * p.H <= lim)
+
     def team_models(self, team_min_size=None) -> int:
         """Number of leading models of the launch order big enough for a team."""
         lim = self.team_min_size if team_min_size is None else team_min_size
@@ -633,7 +650,7 @@ class BatchedPredation:
         k = self.team_size if team_size is None else team_size
         nt = self.team_models(team_min_size) if k > 1 else 0
         return Tuning(block_threads or self.block_threads, workgroups or self.workgroups,
-                      items or self.items, k, nt, team_workgroups)
+                      items or self.items, k, nt, team_workgroups, 0 if self.lds else 1)
 
     def capture(self, chunk_steps: int, n_chunks: int, **tuning) -> "RolloutGraph":
         """A rollout of n_chunks launches of up to chunk_steps steps each,

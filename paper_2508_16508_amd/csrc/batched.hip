@@ -21,6 +21,13 @@
 //                      free slots (alive 0 or 2) are ranked, the free slot of
 //                      rank j < #breeders pulls its child from breeder j, and
 //                      live agents with negative energy die.
+// A model run by one workgroup whose claim table (three words per cell) fits
+// in the workgroup's dynamic LDS keeps it there (LOCAL): the table is set to
+// all-ones when the model is taken, pass A posts into it with LDS atomics, and
+// pass C clears it whole instead of re-arming cell by cell (so C reads no
+// positions).  The global table of such a model is not touched.  The launch
+// gives each workgroup the LDS its occupancy leaves free, so no workgroup
+// is displaced for it.
 // Grass is stored as the step at which a cell is grown again (0 = grown from
 // the start), so the per-cell regrowth pass of the one-model path disappears:
 // a cell is grown at step t iff ready <= t; eating at step t sets ready = t + R.
@@ -53,6 +60,7 @@ struct BatchArgs {
     int64_t scratch_stride;    // ints per workgroup
     uint64_t* err;             // workspace error word
     int32_t n_team;            // order[0, n_team) run in teams
+    int32_t lds_words;         // dynamic LDS claim words per workgroup (0: none)
     uint32_t team_k;           // members per team
     uint32_t team_wgs;         // workgroups in teams (multiple of 8 * team_k)
     uint32_t* team_ctr;        // barrier counter per team
@@ -74,8 +82,26 @@ __device__ __forceinline__ void claim_min(uint64_t* p, uint64_t key) {
     atomicMin(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(key));
 }
 
+// A claim posted into the LOCAL table, through an LDS-qualified pointer (a
+// generic pointer into LDS does not compile for this atomic here).
+__device__ __forceinline__ void claim_min_lds(uint64_t* p, uint64_t key) {
+    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+    __hip_atomic_fetch_min((lds_u64*)p, static_cast<unsigned long long>(key), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void rearm(uint64_t* p) {
     __hip_atomic_store(p, kNoClaim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The LOCAL claim table: the workgroup's dynamic LDS.
+__device__ __forceinline__ uint64_t* local_claims() {
+    extern __shared__ uint64_t dyn_claims[];
+    return dyn_claims;
+}
+
+__device__ __forceinline__ void local_fill(uint64_t* lc, int32_t words) {
+    for (int32_t i = threadIdx.x; i < words; i += blockDim.x) lc[i] = kNoClaim;
 }
 
 __device__ __forceinline__ uint64_t key_of(uint64_t skey, int64_t slot, uint32_t purpose) {
@@ -228,9 +254,18 @@ __device__ __forceinline__ bool team_sync(Team& tm) {
 // is blockDim * ITEMS slots; item k of lane l of wave w is slot
 // c0 + (w * ITEMS + k) * 64 + l, so each load instruction of a wave covers 64
 // consecutive slots and the ITEMS loads of a lane are issued together.
-template <int ITEMS>
+template <int ITEMS, bool LOCAL>
 __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* lds,
                            uint32_t* live_out) {
+    uint64_t* const claims = LOCAL ? local_claims() : v.claims;
+    // LOCAL: the atomics of pass A are complete at the barrier that ends it
+    auto rd = [](const uint64_t* p) { return LOCAL ? *p : ld_claim(p); };
+    auto post = [](uint64_t* p, uint64_t key) {
+        if constexpr (LOCAL)
+            claim_min_lds(p, key);
+        else
+            claim_min(p, key);
+    };
     const uint64_t skey = stream_key(v.seed, t);
     const uint32_t move_p[2] = {kSheepMove, kWolfMove};
     const uint32_t breed_p[2] = {kSheepBreed, kWolfBreed};
@@ -280,12 +315,12 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                 v.e[s][i] -= 1;
                 if (!on_grid(v, x, y)) continue;
                 const int64_t c = int64_t(y) * v.W + x;
-                uint64_t* cw = v.claims + 3 * c;
+                uint64_t* cw = claims + 3 * c;
                 if (s == 0) {
-                    if (v.ready[c] <= int32_t(t)) claim_min(cw + 0, key_of(skey, i, kSheepGrassKey));
-                    claim_min(cw + 1, key_of(skey, i, kSheepPreyKey));
+                    if (v.ready[c] <= int32_t(t)) post(cw + 0, key_of(skey, i, kSheepGrassKey));
+                    post(cw + 1, key_of(skey, i, kSheepPreyKey));
                 } else {
-                    claim_min(cw + 2, key_of(skey, i, kWolfEatKey));
+                    post(cw + 2, key_of(skey, i, kWolfEatKey));
                 }
             }
         }
@@ -318,21 +353,19 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                 bool eaten = false;
                 if (on_grid(v, x, y)) {
                     const int64_t c = int64_t(y) * v.W + x;
-                    const uint64_t* cw = v.claims + 3 * c;
+                    const uint64_t* cw = claims + 3 * c;
                     if (s == 0) {
-                        if (ld_claim(cw + 0) == key_of(skey, i, kSheepGrassKey)) {
+                        if (rd(cw + 0) == key_of(skey, i, kSheepGrassKey)) {
                             e += v.gain[0];
                             v.e[0][i] = e;
                             v.ready[c] = int32_t(t) + v.R;
                         }
-                        if (ld_claim(cw + 2) != kNoClaim &&
-                            ld_claim(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
+                        if (rd(cw + 2) != kNoClaim && rd(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
                             v.al[0][i] = 2;   // eaten: dead, its claims still to be reset
                             eaten = true;
                             ++nfree;
                         }
-                    } else if (ld_claim(cw + 1) != kNoClaim &&
-                               ld_claim(cw + 2) == key_of(skey, i, kWolfEatKey)) {
+                    } else if (rd(cw + 1) != kNoClaim && rd(cw + 2) == key_of(skey, i, kWolfEatKey)) {
                         e += v.gain[1];
                         v.e[1][i] = e;
                     }
@@ -400,6 +433,8 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
     *live_out = uint32_t(fpre[2]);
 
     // ---- C: re-arm claims, breed into free slots, starve
+    // (LOCAL: every read of the table in B is behind the barrier above)
+    if constexpr (LOCAL) local_fill(claims, 3 * v.W * v.H);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int32_t* bpre = s ? bpre1 : bpre0;
@@ -418,11 +453,11 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
                 fr[k] = i < hi[s] && (al[k] == 0 || al[k] == 2);
-                if (i >= hi[s] || al[k] == 0) continue;
+                if (LOCAL || i >= hi[s] || al[k] == 0) continue;
                 // this agent posted claims in A: reset them
                 const int32_t x = v.x[s][i], y = v.y[s][i];
                 if (!on_grid(v, x, y)) continue;
-                uint64_t* cw = v.claims + 3 * (int64_t(y) * v.W + x);
+                uint64_t* cw = claims + 3 * (int64_t(y) * v.W + x);
                 if (s == 0) {
                     rearm(cw + 0);
                     rearm(cw + 1);
@@ -561,7 +596,9 @@ __device__ bool balance_team(const ModelView& v, Team& tm, uint32_t* lds) {
 }
 
 // Runs model m's pending steps (at most max_steps) with team tm; member 0
-// updates the descriptor.  False if a team barrier failed.
+// updates the descriptor.  A model of a single workgroup (no team) keeps its
+// claim table in LDS when its 3 W H words fit in a.lds_words.  False if a
+// team barrier failed.
 template <int ITEMS>
 __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds) {
     abm_model_desc* d = a.models + m;
@@ -577,9 +614,16 @@ __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds
     if (t1 - t0 > a.max_steps) t1 = t0 + a.max_steps;
     if (tm.K > 1 && t1 > t0 && !balance_team<ITEMS>(v, tm, lds)) return false;
     uint64_t updates = 0;
+    const bool local = tm.K == 1 && 3 * int64_t(v.W) * v.H <= a.lds_words;
+    if (local && t1 > t0) {
+        local_fill(local_claims(), 3 * v.W * v.H);
+        __syncthreads();
+    }
     for (int32_t t = t0; t < t1; ++t) {
         uint32_t live;
-        if (!model_step<ITEMS>(v, uint32_t(t), tm, lds, &live)) return false;
+        const bool ok = local ? model_step<ITEMS, true>(v, uint32_t(t), tm, lds, &live)
+                              : model_step<ITEMS, false>(v, uint32_t(t), tm, lds, &live);
+        if (!ok) return false;
         updates += live;
     }
     if (threadIdx.x == 0 && tm.r == 0 && t1 > t0) {
@@ -777,6 +821,64 @@ extern "C" int abm_predation_batched_init(const abm_batch* b, void* stream) {
     return launch_status("predation_batched_init");
 }
 
+namespace {
+
+const void* run_kernel(int items) {
+    return items == 1 ? reinterpret_cast<const void*>(k_batched_run<1>)
+         : items == 2 ? reinterpret_cast<const void*>(k_batched_run<2>)
+                      : reinterpret_cast<const void*>(k_batched_run<4>);
+}
+
+// Launch shape of a run: workgroups resident per CU at `block` threads and
+// the dynamic LDS each can hold without lowering that count (the CU's LDS
+// shared among them, less the kernel's static LDS; at most the per-workgroup
+// limit).  False with the error set if a query fails.
+bool run_shape(int items, int block, int* n_cu, int* per_cu, int64_t* lds_bytes) {
+    const void* kern = run_kernel(items);
+    int dev = 0, lds_cu = 0, lds_block = 0;
+    hipFuncAttributes fa;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        hipFuncGetAttributes(&fa, kern) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, block, 0) != hipSuccess) {
+        set_error("predation_run_batched: device query failed");
+        return false;
+    }
+    if (*per_cu < 1) *per_cu = 1;
+    int64_t dyn = int64_t(lds_cu) / *per_cu - int64_t(fa.sharedSizeBytes);
+    if (dyn > int64_t(lds_block) - int64_t(fa.sharedSizeBytes))
+        dyn = int64_t(lds_block) - int64_t(fa.sharedSizeBytes);
+    dyn = dyn > 0 ? dyn / 1024 * 1024 : 0;
+    // allocation granularity: step down until the occupancy is unchanged
+    for (; dyn > 0; dyn -= 1024) {
+        int with = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&with, kern, block, size_t(dyn)) !=
+            hipSuccess) {
+            set_error("predation_run_batched: occupancy query failed");
+            return false;
+        }
+        if (with >= *per_cu) break;
+    }
+    *lds_bytes = dyn;
+    return true;
+}
+
+}  // namespace
+
+extern "C" int64_t abm_batched_lds_cells(int32_t block_threads, int32_t items) {
+    if (block_threads < 256 || block_threads > 1024 || (block_threads & 63)) return 0;
+    if (items != 1 && items != 2 && items != 4) return 0;
+    if (check_device() != ABM_OK) return 0;
+    int n_cu = 0, per_cu = 0;
+    int64_t lds_bytes = 0;
+    if (!run_shape(items, block_threads, &n_cu, &per_cu, &lds_bytes)) return 0;
+    return lds_bytes / 24;
+}
+
 extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* order,
                                          int32_t max_steps, const abm_tuning* tune, void* ws,
                                          size_t ws_bytes, void* stream) {
@@ -791,18 +893,12 @@ extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* orde
     if (block < 256 || block > 1024 || (block & 63))
         return fail(ABM_E_INVALID, "block_threads must be a multiple of 64 in [256, 1024]");
     const int items = tune && tune->items ? tune->items : 4;
-    if (items != 1 && items != 2 && items != 4 && items != 8)
-        return fail(ABM_E_INVALID, "items must be 1, 2, 4 or 8");
-    const void* kern = items == 1 ? reinterpret_cast<const void*>(k_batched_run<1>)
-                     : items == 2 ? reinterpret_cast<const void*>(k_batched_run<2>)
-                     : items == 4 ? reinterpret_cast<const void*>(k_batched_run<4>)
-                                  : reinterpret_cast<const void*>(k_batched_run<8>);
-    int dev = 0, n_cu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess)
-        return launch_status("predation_run_batched: device query");
-    if (per_cu < 1) per_cu = 1;
+    if (items != 1 && items != 2 && items != 4)
+        return fail(ABM_E_INVALID, "items must be 1, 2 or 4");
+    int n_cu = 0, per_cu = 0;
+    int64_t lds_bytes = 0;
+    if (!run_shape(items, block, &n_cu, &per_cu, &lds_bytes)) return ABM_E_HIP;
+    if (tune && tune->global_claims) lds_bytes = 0;
     int resident = n_cu * per_cu;
     if (tune && tune->workgroups > 0 && tune->workgroups < resident) resident = tune->workgroups;
     if (resident > kMaxWorkgroups) resident = kMaxWorkgroups;
@@ -863,16 +959,17 @@ extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* orde
     a.scratch = reinterpret_cast<int32_t*>(base + kHeaderBytes + 4 * kTeamAreaWords);
     a.scratch_stride = 2 * b->max_cap;
     a.n_team = n_team;
+    a.lds_words = int32_t(lds_bytes / 8);
     a.team_k = uint32_t(K);
     a.team_wgs = uint32_t(team_wgs);
     const int n_teams = team_wgs / K;
     hipLaunchKernelGGL(k_reset_queue, dim3((n_teams + 255) / 256 + 1), dim3(256), 0, st, a.queue,
                        a.team_ctr, n_teams);
+    const size_t dyn = size_t(lds_bytes);
     switch (items) {
-        case 1: hipLaunchKernelGGL(k_batched_run<1>, dim3(grid), dim3(block), 0, st, a); break;
-        case 2: hipLaunchKernelGGL(k_batched_run<2>, dim3(grid), dim3(block), 0, st, a); break;
-        case 4: hipLaunchKernelGGL(k_batched_run<4>, dim3(grid), dim3(block), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_batched_run<8>, dim3(grid), dim3(block), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_batched_run<1>, dim3(grid), dim3(block), dyn, st, a); break;
+        case 2: hipLaunchKernelGGL(k_batched_run<2>, dim3(grid), dim3(block), dyn, st, a); break;
+        default: hipLaunchKernelGGL(k_batched_run<4>, dim3(grid), dim3(block), dyn, st, a); break;
     }
     hipLaunchKernelGGL(k_batched_count, dim3(b->n_models), dim3(256), 0, st, b->models,
                        b->sheep.alive, b->wolves.alive);

@@ -266,7 +266,7 @@ class GpuRunner:
 
     def __init__(self, cell_capacity, sheep_capacity, wolf_capacity, max_active=4096,
                  block_threads=512, items=4, device="cuda", keep_results=False,
-                 max_model_cap=None, team_size=4, team_min_size=1 << 18):
+                 max_model_cap=None, team_size=4, team_min_size=1 << 18, lds=True):
         import torch
 
         import paper_2508_16508_amd as abm
@@ -285,6 +285,8 @@ class GpuRunner:
         self.block_threads, self.items = block_threads, items
         # models of at least team_min_size cells plus slots run on teams of workgroups
         self.team_size, self.team_min_size = team_size, team_min_size
+        # models of one workgroup whose claim table fits keep it in LDS
+        self.lds = lds
         props = torch.cuda.get_device_properties(self.ready.device)
         self.workgroups = props.multi_processor_count * max(1, 2048 // block_threads)
         # breeder scratch per workgroup is sized by the largest single model
@@ -369,7 +371,8 @@ class GpuRunner:
         self.order[:n].copy_(self.h_order[slot][:n], non_blocking=True)
         b = self._batch(self.desc, n)
         n_team = sum(1 for r in models if self._team_model(r))
-        t = abm.Tuning(self.block_threads, self.workgroups, self.items, self.team_size, n_team, 0)
+        t = abm.Tuning(self.block_threads, self.workgroups, self.items, self.team_size, n_team, 0,
+                       0 if self.lds else 1)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)

@@ -14,7 +14,7 @@ import os
 
 import torch
 
-CANDIDATES = ((256, 1), (256, 2), (256, 4), (512, 2), (512, 4), (512, 8), (1024, 4), (1024, 8))
+CANDIDATES = ((256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4), (1024, 2), (1024, 4))
 
 
 def default_cache_path() -> str:

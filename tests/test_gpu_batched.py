@@ -61,7 +61,7 @@ def _mixed_models(seed, n):
     return out
 
 
-@pytest.mark.parametrize("block,items", [(256, 1), (512, 2), (512, 4), (1024, 8)])
+@pytest.mark.parametrize("block,items", [(256, 1), (512, 2), (512, 4), (1024, 2)])
 def test_mixed_batch_matches_models_alone(abm, orc, block, items):
     """40 models of random shapes (1x1 up to 40x40, tiny and overflowing
     capacities, different regrowth delays, seeds and reproduction rates),
@@ -304,8 +304,9 @@ def test_full_workload_graph_replay(abm, orc):
     50-step persistent launches.  Every model's whole state and counters
     equal those of the same batch advanced without a graph, with another
     launch shape (1024 x 4, teams of 4 for the 64 largest models, 100-step
-    launches); 48 models across the sizes equal the one-model multi-launch
-    path; 12 of them equal the oracle."""
+    launches, every claim table global, where the benchmark keeps the
+    smallest models' tables in LDS); 48 models across the sizes equal the
+    one-model multi-launch path; 12 of them equal the oracle."""
     specs = W.batched_models(0, 4096)
     kws = [dict(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s, cap_w=sp.cap_w,
                 n_s0=sp.n_s0, n_w0=sp.n_w0) for sp in specs]
@@ -316,8 +317,9 @@ def test_full_workload_graph_replay(abm, orc):
     a.run(1)
     graph = a.capture(50, 10)
     graph.replay()
+    assert a.lds_models() > 0
     b = abm.BatchedPredation(params, steps, block_threads=1024, items=4, team_size=4,
-                             team_min_size=a.sorted_size[63])
+                             team_min_size=a.sorted_size[63], lds=False)
     b.init()
     for _ in range(5):
         b.run(100)
@@ -347,3 +349,54 @@ def test_full_workload_graph_replay(abm, orc):
     for m in pick[::4]:
         _check_model(abm, orc, a, m, kws[m], steps, ca)
     graph.destroy()
+
+
+def test_lds_claim_tables_match_global_ones(abm, orc):
+    """Models on both sides of the LDS limit of each launch shape (claim tables
+    of 24 bytes per cell) run with claims in LDS where they fit and with every
+    claim table global: identical bytes, the global claim table all-ones after
+    every run, and models on both sides of the limit match the oracle."""
+    props = torch.cuda.get_device_properties(0)
+    for block, items in ((512, 2), (1024, 4), (256, 1)):
+        lim = int(abm.lib().abm_batched_lds_cells(block, items))
+        assert 1024 <= lim and 24 * lim <= getattr(props, "shared_memory_per_block", 24 * lim)
+        side = int(np.sqrt(lim))
+        g = np.random.default_rng(block + items)
+        kws = []
+        for (Wd, Hd) in ((side, side), (side + 1, side + 1), (lim, 1), (1, lim + 1), (3, 5),
+                         (side + 20, side), (17, 40)):
+            cells = Wd * Hd
+            kws.append(dict(W=Wd, H=Hd, seed=int(g.integers(0, 2 ** 32)), cap_s=cells // 2 + 1,
+                            cap_w=cells // 8 + 1, n_s0=cells // 10, n_w0=cells // 40 + 1,
+                            R=int(g.integers(1, 12))))
+        params = [abm.predation_params(**kw) for kw in kws]
+        out = []
+        for lds in (True, False):
+            b = abm.BatchedPredation(params, 45, block_threads=block, items=items, lds=lds)
+            assert b.lds_models() == (4 if lds else 0)
+            b.init()
+            for steps in (20, 25):
+                b.run(steps)
+            torch.cuda.synchronize()
+            assert abm.workspace_error(b.ws) == 0
+            assert bool((b.claims.view(torch.int64) == -1).all()), lds
+            out.append(b)
+        cds = [b.grass_countdown() for b in out]
+        assert torch.equal(cds[0], cds[1])
+        for f in FIELDS:
+            assert torch.equal(out[0].sheep[f], out[1].sheep[f])
+            assert torch.equal(out[0].wolves[f], out[1].wolves[f])
+        for d0, d1 in zip(out[0].descriptors(), out[1].descriptors()):
+            assert (d0.step, d0.updates, d0.live_s, d0.live_w) == \
+                (d1.step, d1.updates, d1.live_s, d1.live_w)
+        for m in (0, 1, 4):
+            _check_model(abm, orc, out[0], m, kws[m], 45, cds[0])
+        del out, cds
+        torch.cuda.empty_cache()
+
+
+def test_lds_cells_rejects_bad_shapes(abm):
+    assert abm.lib().abm_batched_lds_cells(100, 2) == 0
+    assert abm.lib().abm_batched_lds_cells(512, 8) == 0
+    # fewer workgroups resident per CU leave each more LDS
+    assert abm.lib().abm_batched_lds_cells(1024, 1) >= abm.lib().abm_batched_lds_cells(256, 1)
