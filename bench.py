@@ -36,7 +36,7 @@ N_ATTRS = 8
 
 
 LEGS = ("predation_small", "predation_large", "predation_large_multi_prey", "traffic", "lob",
-        "sort_select", "batched")
+        "sort_select", "batched", "batched_multi_prey")
 
 
 def algorithmic_bytes(op, n, k):
@@ -425,6 +425,47 @@ def lob_leg(abm, torch, n_books=500, cap=1000, traders=100, steps=100):
             "book_steps_per_s": n_books * steps / (ms / 1e3)}
 
 
+def batched_multi_prey_leg(abm, W, torch, steps=200, chunk=50, block=512, items=2):
+    """The 4096-model batch of the batched leg with multi-prey (the wolves and
+    sheep of a cell paired by rank) in every model, run as `steps` launches of
+    `chunk` steps at one fixed shape after a warm-up step, against the same
+    batch with the one-prey rule at that shape."""
+    specs = W.batched_models(0, 4096)
+    out = {"workload": "4096 predation models as in the batched leg, multi-prey in every model; "
+                       f"{steps} timed steps as {steps // chunk} persistent launches of {chunk} "
+                       f"steps, {block} threads x {items} items",
+           "block_threads": block, "items": items}
+    for multi in (1, 0):
+        params = [abm.predation_params(W=sp.side, H=sp.side, seed=sp.seed, cap_s=sp.cap_s,
+                                       cap_w=sp.cap_w, n_s0=sp.n_s0, n_w0=sp.n_w0,
+                                       multi_prey=multi) for sp in specs]
+        b = abm.BatchedPredation(params, steps + 1, block_threads=block, items=items)
+        b.init()
+        b.run(1)
+        torch.cuda.synchronize()
+        u0 = sum(d.updates for d in b.descriptors())
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps // chunk):
+            b.run(chunk)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        d1 = b.descriptors()
+        assert all(d.step == steps + 1 for d in d1)
+        rate = (sum(d.updates for d in d1) - u0) / (ms / 1e3)
+        err = abm.workspace_error(b.ws)
+        if multi:
+            out.update(ms=ms, agent_updates_per_s=rate, workspace_error=err)
+        else:
+            out.update(one_prey_ms=ms, one_prey_agent_updates_per_s=rate)
+            out["workspace_error"] = max(out["workspace_error"], err)
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def traffic_leg(abm, torch, n_roads=500, length=100, steps=1000):
     """Traffic CA (Sec. 5.2): n_roads roads of 3 x length cells, `steps` steps in
     one call (one workgroup per road, the road held in LDS); car updates per
@@ -668,6 +709,8 @@ def main():
     if "batched" in legs:
         out["batched"] = batched_leg(abm, W, torch, lds=args.batched_lds == "on",
                                      max_side=args.batched_max_side)
+    if "batched_multi_prey" in legs:
+        out["batched_multi_prey"] = batched_multi_prey_leg(abm, W, torch)
     torch.cuda.empty_cache()
     if args.served_seconds > 0:
         out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)
@@ -675,7 +718,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seeds)
     for leg in ("predation_small", "predation_large", "predation_large_multi_prey", "batched",
-                "served"):
+                "batched_multi_prey", "served"):
         if leg in out:
             out["workspace_error"][leg] = out[leg]["workspace_error"]
     print(json.dumps(out), flush=True)

@@ -211,8 +211,7 @@ typedef struct abm_predation_params {
     uint32_t seed;
     int64_t cap_s, cap_w;  /* slot capacities, 1 <= cap < 2^31 */
     int64_t n_s0, n_w0;    /* initial live agents (slots 0 .. n0-1), n0 <= cap */
-    int32_t multi_prey;    /* 0: one prey per cell; 1: prey matched by rank within a cell
-                              (abm_predation_step only; the batched form has the one-prey rule) */
+    int32_t multi_prey;    /* 0: one prey per cell; 1: prey matched by rank within a cell */
 } abm_predation_params;
 
 typedef struct abm_species {
@@ -294,11 +293,17 @@ ABM_API int abm_resolve_conflicts_batched(int32_t n_segments, const int64_t* cla
  * [sheep_off, sheep_off + cap_s) / [wolf_off, wolf_off + cap_w) of the species
  * arrays.  Ranges must not overlap.  `ready` holds the step at which a cell is
  * grown again (grown at step t iff ready <= t); abm_predation_batched_grass
- * converts it to the countdown form of abm_predation_state.
+ * converts it to the countdown form of abm_predation_state.  A model with
+ * multi_prey set links its agents into per-cell lists through slots
+ * [sheep_off, sheep_off + cap_s) of link_s and [wolf_off, wolf_off + cap_w)
+ * of link_w; a run leaves such a model untouched and sets the workspace error
+ * word if the batch has no links.
  * ------------------------------------------------------------------------- */
 typedef struct abm_model_desc {   /* device array; the library updates the last five fields */
     int32_t W, H, R, gain_s, gain_w;
     uint32_t T_s, T_w, seed;
+    int32_t multi_prey;            /* 0: one prey per cell; nonzero: prey matched by rank within a
+                                      cell (as abm_predation_params; needs the batch's links) */
     int64_t cap_s, cap_w;          /* each in [1, 2^30] */
     int64_t n_s0, n_w0;
     int64_t cell_off, sheep_off, wolf_off;
@@ -315,6 +320,8 @@ typedef struct abm_batch {        /* host struct of device pointers */
     int32_t* ready;                /* device int32[sum of W*H] */
     uint64_t* claims;              /* device uint64[3 * sum of W*H]; set by init, kept all-ones between runs */
     abm_species sheep, wolves;     /* device int32[sum of caps] each */
+    int32_t* link_s;               /* device int32[sum of cap_s] and [sum of cap_w]: per-cell lists */
+    int32_t* link_w;               /* of multi-prey models (scratch; NULL if no model has multi_prey) */
 } abm_batch;
 
 typedef struct abm_tuning {

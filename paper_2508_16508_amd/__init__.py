@@ -95,7 +95,7 @@ class PredationStatePtrs(C.Structure):
 class Batch(C.Structure):
     _fields_ = [("n_models", C.c_int32), ("max_cap", C.c_int64), ("models", C.c_void_p),
                 ("ready", C.c_void_p), ("claims", C.c_void_p), ("sheep", SpeciesPtrs),
-                ("wolves", SpeciesPtrs)]
+                ("wolves", SpeciesPtrs), ("link_s", C.c_void_p), ("link_w", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -519,7 +519,7 @@ def predation_params(W=64, H=64, R=30, gain_s=4, gain_w=20, T_s=171798691, T_w=2
                      multi_prey=0) -> PredationParams:
     """Defaults: the small 64x64 workload (regrowth 30, gains 4 / 20,
     reproduction 0.04 / 0.05 as floor(p * 2^32)).  multi_prey = 1: wolves and
-    sheep of a cell are matched by rank (one-model path only)."""
+    sheep of a cell are matched by rank."""
     return PredationParams(W, H, R, gain_s, gain_w, T_s, T_w, seed, cap_s, cap_w, n_s0, n_w0,
                            multi_prey)
 
@@ -546,7 +546,7 @@ class ModelDesc(C.Structure):
     _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("R", C.c_int32),
                 ("gain_s", C.c_int32), ("gain_w", C.c_int32),
                 ("T_s", C.c_uint32), ("T_w", C.c_uint32), ("seed", C.c_uint32),
-                ("cap_s", C.c_int64), ("cap_w", C.c_int64),
+                ("multi_prey", C.c_int32), ("cap_s", C.c_int64), ("cap_w", C.c_int64),
                 ("n_s0", C.c_int64), ("n_w0", C.c_int64),
                 ("cell_off", C.c_int64), ("sheep_off", C.c_int64), ("wolf_off", C.c_int64),
                 ("step", C.c_int32), ("steps_target", C.c_int32),
@@ -566,8 +566,6 @@ class BatchedPredation:
     def __init__(self, models, steps_target, device="cuda", block_threads=512, items=4,
                  team_size=1, team_min_size=1 << 18, lds=True):
         self.params = list(models)
-        if any(getattr(p, "multi_prey", 0) for p in self.params):
-            raise ValueError("the batched form implements the one-prey rule only (multi_prey = 0)")
         n = len(self.params)
         tgt = [steps_target] * n if isinstance(steps_target, int) else list(steps_target)
         self.n_models = n
@@ -575,8 +573,8 @@ class BatchedPredation:
         g_off = s_off = w_off = 0
         for m, p in enumerate(self.params):
             d = descs[m]
-            for f in ("W", "H", "R", "gain_s", "gain_w", "T_s", "T_w", "seed", "cap_s", "cap_w",
-                      "n_s0", "n_w0"):
+            for f in ("W", "H", "R", "gain_s", "gain_w", "T_s", "T_w", "seed", "multi_prey",
+                      "cap_s", "cap_w", "n_s0", "n_w0"):
                 setattr(d, f, getattr(p, f))
             d.cell_off, d.sheep_off, d.wolf_off = g_off, s_off, w_off
             d.step, d.steps_target = 0, int(tgt[m])
@@ -590,6 +588,9 @@ class BatchedPredation:
         self.claims = torch.empty(3 * max(1, g_off), dtype=torch.uint64, device=device)
         self.sheep = {f: z(s_off) for f in ("x", "y", "e", "alive")}
         self.wolves = {f: z(w_off) for f in ("x", "y", "e", "alive")}
+        # per-cell list links, needed only by multi-prey models
+        multi = any(p.multi_prey for p in self.params)
+        self.links = (z(s_off), z(w_off)) if multi else None
         raw = bytes(descs)
         self.desc = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
         size = [p.W * p.H + p.cap_s + p.cap_w for p in self.params]
@@ -613,8 +614,9 @@ class BatchedPredation:
 
     def _batch(self) -> Batch:
         sp = lambda d: SpeciesPtrs(*(d[k].data_ptr() for k in ("x", "y", "e", "alive")))
+        ls, lw = (t.data_ptr() for t in self.links) if self.links else (None, None)
         return Batch(self.n_models, self.max_cap, self.desc.data_ptr(), self.ready.data_ptr(),
-                     self.claims.data_ptr(), sp(self.sheep), sp(self.wolves))
+                     self.claims.data_ptr(), sp(self.sheep), sp(self.wolves), ls, lw)
 
     def init(self, stream=None):
         b = self._batch()

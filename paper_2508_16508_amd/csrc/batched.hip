@@ -15,6 +15,10 @@
 //                      words; grass winners gain and set the cell's regrowth
 //                      step, eaten sheep are marked alive = 2 (dead, claims not
 //                      yet cleared); breeders are compacted in slot order;
+//                      (multi-prey models: in A the agents push themselves onto
+//                      lists of their cell instead of posting prey and eater
+//                      keys, and a pass between A and B pairs each cell's
+//                      wolves and sheep by rank; see prey_match)
 //   C  re-arm + breed  every agent that was live at the start of the step
 //                      resets the claim words it posted (so the tables return
 //                      to all-ones after touching only occupied cells), then
@@ -59,6 +63,7 @@ struct BatchArgs {
     int32_t* scratch;          // per-workgroup breeder list
     int64_t scratch_stride;    // ints per workgroup
     uint64_t* err;             // workspace error word
+    int32_t *link_s, *link_w;  // per-cell list links of multi-prey models (or null)
     int32_t n_team;            // order[0, n_team) run in teams
     int32_t lds_words;         // dynamic LDS claim words per workgroup (0: none)
     uint32_t team_k;           // members per team
@@ -88,6 +93,18 @@ __device__ __forceinline__ void claim_min_lds(uint64_t* p, uint64_t key) {
     typedef __attribute__((address_space(3))) unsigned long long lds_u64;
     __hip_atomic_fetch_min((lds_u64*)p, static_cast<unsigned long long>(key), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Pushes slot onto the list whose head is *p; returns the previous head.
+__device__ __forceinline__ uint64_t push_head(uint64_t* p, int32_t slot) {
+    return __hip_atomic_exchange(p, uint64_t(uint32_t(slot)), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t push_head_lds(uint64_t* p, int32_t slot) {
+    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+    return __hip_atomic_exchange((lds_u64*)p, static_cast<unsigned long long>(uint32_t(slot)),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void rearm(uint64_t* p) {
@@ -174,7 +191,9 @@ __device__ __forceinline__ uint32_t chunk_rank(const bool (&f)[ITEMS], uint32_t 
 struct ModelView {
     int32_t W, H, R, gain[2];
     uint32_t T[2], seed;
+    bool multi;                  // prey matched by rank within a cell
     int32_t cap[2];
+    int32_t* link[2];            // list links (multi), per species
     int32_t* ready;
     uint64_t* claims;
     int32_t *x[2], *y[2], *e[2], *al[2];
@@ -250,6 +269,35 @@ __device__ __forceinline__ bool team_sync(Team& tm) {
     return *tm.s_ok != 0;
 }
 
+// Multi-prey rule for wolf j whose cell's words are cw (Sec. 4, Alg. 1 applied
+// within one cell): j has rank r among the cell's wolves by eat key and takes
+// the sheep of rank r among the cell's sheep by prey key, if there is one,
+// marking it alive = 2 and gaining.  Ranks are counted by walking the cell's
+// lists, whose heads are the prey (sheep) and eater (wolf) words; distinct
+// wolves have distinct ranks, so no sheep is taken twice.  Quadratic in the
+// sheep of one cell, which are few at the workloads' densities.
+template <class Read>
+__device__ __forceinline__ void prey_match(const ModelView& v, uint64_t skey, const uint64_t* cw,
+                                           int32_t j, Read rd) {
+    const int32_t first = int32_t(uint32_t(rd(cw + 1)));
+    if (first < 0) return;
+    const uint64_t mine = key_of(skey, j, kWolfEatKey);
+    uint32_t r = 0;
+    for (int32_t w = int32_t(uint32_t(rd(cw + 2))); w >= 0; w = v.link[1][w])
+        r += key_of(skey, w, kWolfEatKey) < mine ? 1u : 0u;
+    for (int32_t q = first; q >= 0; q = v.link[0][q]) {
+        const uint64_t kq = key_of(skey, q, kSheepPreyKey);
+        uint32_t below = 0;
+        for (int32_t u = first; u >= 0; u = v.link[0][u])
+            below += key_of(skey, u, kSheepPreyKey) < kq ? 1u : 0u;
+        if (below == r) {
+            v.al[0][q] = 2;
+            v.e[1][j] += v.gain[1];
+            return;
+        }
+    }
+}
+
 // One step t of model v by team tm; false if the team barrier failed.  A chunk
 // is blockDim * ITEMS slots; item k of lane l of wave w is slot
 // c0 + (w * ITEMS + k) * 64 + l, so each load instruction of a wave covers 64
@@ -265,6 +313,11 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
             claim_min_lds(p, key);
         else
             claim_min(p, key);
+    };
+    // multi-prey: the agent's link is the cell's previous head (kNoClaim: -1, the end)
+    auto push = [](uint64_t* p, int32_t slot, int32_t* link) {
+        const uint64_t prev = LOCAL ? push_head_lds(p, slot) : push_head(p, slot);
+        link[slot] = int32_t(uint32_t(prev));
     };
     const uint64_t skey = stream_key(v.seed, t);
     const uint32_t move_p[2] = {kSheepMove, kWolfMove};
@@ -318,7 +371,12 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                 uint64_t* cw = claims + 3 * c;
                 if (s == 0) {
                     if (v.ready[c] <= int32_t(t)) post(cw + 0, key_of(skey, i, kSheepGrassKey));
-                    post(cw + 1, key_of(skey, i, kSheepPreyKey));
+                    if (v.multi)
+                        push(cw + 1, i, v.link[0]);
+                    else
+                        post(cw + 1, key_of(skey, i, kSheepPreyKey));
+                } else if (v.multi) {
+                    push(cw + 2, i, v.link[1]);
                 } else {
                     post(cw + 2, key_of(skey, i, kWolfEatKey));
                 }
@@ -327,6 +385,21 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
     }
     live = block_sum32(live, lds);
     if (!team_sync(tm)) return false;    // every claim of the step is posted
+
+    // ---- multi-prey: wolves of this member take their prey
+    if (v.multi) {
+        for (int32_t c0 = lo[1]; c0 < hi[1]; c0 += chunk) {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const int32_t j = c0 + lbase + k * 64;
+                if (j >= hi[1] || v.al[1][j] == 0) continue;
+                const int32_t x = v.x[1][j], y = v.y[1][j];
+                if (!on_grid(v, x, y)) continue;
+                prey_match(v, skey, claims + 3 * (int64_t(y) * v.W + x), j, rd);
+            }
+        }
+        if (!team_sync(tm)) return false;   // eaten sheep and wolves' gains are visible
+    }
 
     // ---- B: eat, member-local breeder lists (ascending), free-slot counts
     uint32_t nb_local[2], nf_local[2];
@@ -360,12 +433,16 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                             v.e[0][i] = e;
                             v.ready[c] = int32_t(t) + v.R;
                         }
-                        if (rd(cw + 2) != kNoClaim && rd(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
+                        if (v.multi) {
+                            eaten = al[k] == 2;   // taken by a wolf of its cell
+                        } else if (rd(cw + 2) != kNoClaim &&
+                                   rd(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
                             v.al[0][i] = 2;   // eaten: dead, its claims still to be reset
                             eaten = true;
-                            ++nfree;
                         }
-                    } else if (rd(cw + 1) != kNoClaim && rd(cw + 2) == key_of(skey, i, kWolfEatKey)) {
+                        nfree += eaten ? 1u : 0u;
+                    } else if (!v.multi && rd(cw + 1) != kNoClaim &&
+                               rd(cw + 2) == key_of(skey, i, kWolfEatKey)) {
                         e += v.gain[1];
                         v.e[1][i] = e;
                     }
@@ -505,6 +582,9 @@ __device__ ModelView view_of(const BatchArgs& a, const abm_model_desc* d) {
     v.T[0] = d->T_s;
     v.T[1] = d->T_w;
     v.seed = d->seed;
+    v.multi = d->multi_prey != 0;
+    v.link[0] = a.link_s ? a.link_s + d->sheep_off : nullptr;
+    v.link[1] = a.link_w ? a.link_w + d->wolf_off : nullptr;
     v.cap[0] = int32_t(d->cap_s);
     v.cap[1] = int32_t(d->cap_w);
     v.ready = a.ready + d->cell_off;
@@ -602,9 +682,10 @@ __device__ bool balance_team(const ModelView& v, Team& tm, uint32_t* lds) {
 template <int ITEMS>
 __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds) {
     abm_model_desc* d = a.models + m;
-    if (d->cap_s + d->cap_w > a.scratch_stride) {
-        // the descriptor does not fit the breeder list (max_cap too small):
-        // leave the model untouched and report it
+    if (d->cap_s + d->cap_w > a.scratch_stride || (d->multi_prey && !(a.link_s && a.link_w))) {
+        // the descriptor does not fit the breeder list (max_cap too small), or
+        // a multi-prey model has no list links: leave the model untouched and
+        // report it
         if (threadIdx.x == 0 && tm.r == 0) st_agent(tm.err, 1ull);
         return true;
     }
@@ -950,6 +1031,8 @@ extern "C" int abm_predation_run_batched(const abm_batch* b, const int32_t* orde
     a.wy = b->wolves.y;
     a.we = b->wolves.e;
     a.wa = b->wolves.alive;
+    a.link_s = b->link_s;
+    a.link_w = b->link_w;
     char* base = static_cast<char*>(ws);
     a.queue = reinterpret_cast<uint32_t*>(base);
     a.err = reinterpret_cast<uint64_t*>(base + kHeaderBytes - 8);

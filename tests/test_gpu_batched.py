@@ -400,3 +400,101 @@ def test_lds_cells_rejects_bad_shapes(abm):
     assert abm.lib().abm_batched_lds_cells(512, 8) == 0
     # fewer workgroups resident per CU leave each more LDS
     assert abm.lib().abm_batched_lds_cells(1024, 1) >= abm.lib().abm_batched_lds_cells(256, 1)
+
+
+def _multi_models(seed):
+    """Crowded multi-prey tori (tens of each species on one cell, more sheep
+    than wolves and the reverse), the 64x64 workload with multi-prey, and
+    one-prey models beside them."""
+    g = np.random.default_rng(seed)
+    kws = []
+    for (Wd, Hd, cs, cw, ns, nw) in ((1, 1, 40, 20, 12, 6), (2, 1, 30, 30, 14, 14),
+                                     (3, 3, 60, 40, 30, 25), (17, 9, 5000, 3000, 900, 400),
+                                     (1, 1, 25, 60, 5, 30)):
+        kws.append(dict(W=Wd, H=Hd, R=3, T_s=2 ** 30, T_w=2 ** 30,
+                        seed=int(g.integers(0, 2 ** 32)), cap_s=cs, cap_w=cw, n_s0=ns, n_w0=nw,
+                        multi_prey=1))
+    kws.append(dict(seed=int(g.integers(0, 2 ** 32)), multi_prey=1))
+    kws.append(dict(W=150, H=120, seed=int(g.integers(0, 2 ** 32)), cap_s=9000, cap_w=3000,
+                    n_s0=3000, n_w0=1500, multi_prey=1))
+    kws += _mixed_models(seed + 3, 6)
+    return kws
+
+
+@pytest.mark.parametrize("block,items,lds", [(512, 2, True), (256, 1, False), (1024, 4, True)])
+def test_multi_prey_models_in_a_batch(abm, orc, block, items, lds):
+    """Multi-prey models (prey matched by rank within each cell) beside
+    one-prey models in one batch, claims in LDS where they fit or all global,
+    over two launches: every model matches the oracle run alone, and the
+    global claim table (list heads included) is all-ones afterwards."""
+    kws = _multi_models(block + items)
+    targets = [24, 24, 24, 24, 24, 60, 30] + [20] * 6
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], targets,
+                                 block_threads=block, items=items, lds=lds)
+    assert batch.links is not None
+    batch.init()
+    batch.run(11)
+    batch.run(60)
+    torch.cuda.synchronize()
+    assert abm.workspace_error(batch.ws) == 0
+    assert bool((batch.claims.view(torch.int64) == -1).all())
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, targets[m], cd)
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_multi_prey_teams_match_models_alone(abm, orc, K):
+    """Multi-prey models large enough for teams (the lists of a cell hold
+    agents of several members): every model matches the oracle."""
+    g = np.random.default_rng(K)
+    kws = [dict(W=120, H=100, seed=int(g.integers(0, 2 ** 32)), cap_s=9600, cap_w=4800,
+                n_s0=4000, n_w0=2400, multi_prey=1),
+           dict(W=40, H=30, seed=int(g.integers(0, 2 ** 32)), cap_s=20000, cap_w=9000,
+                n_s0=6000, n_w0=3000, multi_prey=1, T_s=2 ** 30, T_w=2 ** 30),
+           dict(W=100, H=100, seed=int(g.integers(0, 2 ** 32)), cap_s=12000, cap_w=2500,
+                n_s0=3000, n_w0=800)]
+    kws += _mixed_models(K + 10, 5)
+    batch = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 30, team_size=K,
+                                 team_min_size=6000)
+    assert batch.team_models() == 3
+    batch.init()
+    batch.run(13)
+    batch.run(17)
+    torch.cuda.synchronize()
+    assert abm.workspace_error(batch.ws) == 0
+    cd = batch.grass_countdown()
+    for m, kw in enumerate(kws):
+        _check_model(abm, orc, batch, m, kw, 30, cd)
+
+
+def test_multi_prey_batched_equals_one_model_path(abm):
+    """A 512x512 multi-prey model at the workload's densities, advanced 40
+    steps by a team of 8 and alone on the one-model path: identical bytes."""
+    L = 512
+    kw = dict(W=L, H=L, seed=91, cap_s=4 * (L * L // 10), cap_w=4 * (L * L // 40),
+              n_s0=L * L // 10, n_w0=L * L // 40, multi_prey=1)
+    b = abm.BatchedPredation([abm.predation_params(**kw)], 40, team_size=8, team_min_size=1)
+    b.init()
+    b.run(40)
+    plain = abm.predation_init(abm.predation_params(**kw))
+    plain.run(40)
+    torch.cuda.synchronize()
+    assert abm.workspace_error(b.ws) == 0
+    grass, sheep, wolves = b.model_state(0)
+    assert torch.equal(grass, plain.grass)
+    for f in FIELDS:
+        assert torch.equal(sheep[f], plain.sheep[f]) and torch.equal(wolves[f], plain.wolves[f])
+
+
+def test_multi_prey_model_without_links_is_left_untouched(abm):
+    kws = [dict(W=20, H=20, seed=1, multi_prey=1, cap_s=400, cap_w=100, n_s0=40, n_w0=10),
+           dict(W=20, H=20, seed=2, cap_s=400, cap_w=100, n_s0=40, n_w0=10)]
+    b = abm.BatchedPredation([abm.predation_params(**kw) for kw in kws], 5)
+    b.init()
+    b.links = None                    # the batch now passes no links
+    b.run(5)
+    torch.cuda.synchronize()
+    d = b.descriptors()
+    assert abm.workspace_error(b.ws) == 1
+    assert (d[0].step, d[1].step) == (0, 5)

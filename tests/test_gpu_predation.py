@@ -198,8 +198,3 @@ def test_multi_prey_large_workload(abm, orc):
         assert st[t + 1][1] == live_w - sw + bw, t
         assert se <= min(live_s, live_w)
     assert abm.workspace_error(model.ws) == 0
-
-
-def test_multi_prey_rejected_by_the_batched_form(abm):
-    with pytest.raises(ValueError):
-        abm.BatchedPredation([abm.predation_params(multi_prey=1)], 5)
