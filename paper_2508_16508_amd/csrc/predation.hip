@@ -12,8 +12,8 @@
 // agents per thread in flight, so dense and sparse tiles alike keep every
 // lane busy.  Step t is three launches (each arrow a grid-wide dependency):
 //   K1 move+claim   every live agent moves, pays 1 energy and posts its
-//                   packed (draw << 32 | slot) key with a 64-bit atomicMin into
-//                   the claim tables of its cell: grass (sheep on grown
+//                   packed (step tag, draw, slot) key with a 64-bit atomicMin
+//                   into the claim tables of its cell: grass (sheep on grown
 //                   cells), prey (sheep) and eater (wolves).
 //   K2 eat+breeders each live agent compares its keys with the reduced table
 //                   entries (grass winner, eaten sheep, eating wolf), applies
@@ -21,8 +21,9 @@
 //                   decides whether it breeds; breeders are compacted into an
 //                   ascending list with the single-pass scan (one scan chain
 //                   per species).
-//   K3 breed+die    the claim tables are re-armed for the next step (each
-//                   workgroup streams its slice); free slots (alive == 0, or
+//   K3 breed+die    at the end of a tag period the claim tables are re-armed
+//                   (each workgroup streams its slice; within a period the
+//                   falling tags make older words lose, see claim_key); free slots (alive == 0, or
 //                   eaten this step) are ranked by the same scan, and the free
 //                   slot of rank j <
 //                   #breeders PULLS its child from breeder j (cell, half the
@@ -48,6 +49,7 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kBlock = 256;
 constexpr int64_t kTile = int64_t(kBlock) * 32;   // 8192 slots: one bitmask word per thread
+constexpr uint32_t kTagBits = 4;                  // claim-key tag: periods of 14 steps
 #ifndef ABM_PRED_IN_FLIGHT
 #define ABM_PRED_IN_FLIGHT 4
 #endif
@@ -82,6 +84,10 @@ struct StepArgs {
     uint64_t* claims;     // three words per cell c, at 3 c: grass (the lowest key
                           // of a sheep on the grown cell), prey (lowest sheep
                           // key), eater (lowest wolf key); together in one line
+    uint32_t sb;          // slot bits of a claim key (see claim_key)
+    uint64_t tag_hi;      // this step's tag, in place
+    uint64_t tag_mask;    // the tag field
+    int32_t rearm;        // K3 re-arms the whole table (the tag period ends)
     int64_t* stats;       // this step's row of 8, or null
     int64_t* acc;         // kAccCounters x kAccLanes spread accumulators
     uint32_t step;
@@ -108,6 +114,27 @@ __device__ __forceinline__ int64_t cell_of(int32_t x, int32_t y, int32_t W, int3
 
 __device__ __forceinline__ uint64_t agent_key(uint64_t skey, int64_t slot, uint32_t purpose) {
     return (uint64_t(draw(skey, uint32_t(slot), purpose)) << 32) | uint32_t(slot);
+}
+
+// A claim word holds (tag, draw, slot) from the high bits down: slot in the
+// low sb bits, the 32-bit draw above it and the step's tag on top.  Within a
+// step, keys order as (draw, slot), the order of the method's claims.  Tags
+// fall from step to step, so a word left by an earlier step of the same
+// period (a larger tag) loses to every fresh claim and reads as unclaimed,
+// and the table need not be re-armed between the steps of a period; all-ones
+// (the re-armed word) carries a tag no step uses.
+__device__ __forceinline__ uint64_t claim_key(const StepArgs& a, uint64_t skey, int64_t slot,
+                                              uint32_t purpose) {
+    return a.tag_hi | (uint64_t(draw(skey, uint32_t(slot), purpose)) << a.sb) | uint64_t(slot);
+}
+
+__device__ __forceinline__ bool claimed(const StepArgs& a, uint64_t word) {
+    return (word & a.tag_mask) == a.tag_hi;
+}
+
+// Slot at the head of a multi-prey list word, or -1 (no push this step).
+__device__ __forceinline__ int32_t head_slot(const StepArgs& a, uint64_t word) {
+    return claimed(a, word) ? int32_t(word & ~a.tag_mask) : -1;
 }
 
 // Block-wide sum of one value per thread, added by thread 0 to this block's
@@ -299,23 +326,24 @@ __global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
         for (int q = 0; q < kInFlight; ++q) {
             if (!on[q] || c[q] < 0) continue;
             if (a.multi) {
-                // push slot i onto the list of its cell; the list ends at all-ones
+                // push slot i onto the list of its cell; the list ends at a word
+                // of an earlier step (or all-ones)
                 if (s == 0 && grown(a.ready[c[q]], a.step))
                     atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q]),
-                              (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
+                              (unsigned long long)claim_key(a, skey, i[q], kSheepGrassKey));
                 uint64_t* head = a.claims + 3 * c[q] + (s ? 2 : 1);
                 const uint64_t prev = atomicExch(reinterpret_cast<unsigned long long*>(head),
-                                                 (unsigned long long)i[q]);
-                a.blist[s][i[q]] = int32_t(prev);   // all-ones -> -1
+                                                 (unsigned long long)(a.tag_hi | uint64_t(i[q])));
+                a.blist[s][i[q]] = head_slot(a, prev);
             } else if (s == 0) {
                 if (grown(a.ready[c[q]], a.step))
                     atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q]),
-                              (unsigned long long)agent_key(skey, i[q], kSheepGrassKey));
+                              (unsigned long long)claim_key(a, skey, i[q], kSheepGrassKey));
                 atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q] + 1),
-                          (unsigned long long)agent_key(skey, i[q], kSheepPreyKey));
+                          (unsigned long long)claim_key(a, skey, i[q], kSheepPreyKey));
             } else {
                 atomicMin(reinterpret_cast<unsigned long long*>(a.claims + 3 * c[q] + 2),
-                          (unsigned long long)agent_key(skey, i[q], kWolfEatKey));
+                          (unsigned long long)claim_key(a, skey, i[q], kWolfEatKey));
             }
         }
     }
@@ -336,9 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_prey_match(StepArgs a) {
     const uint64_t skey = stream_key(a.seed, a.step);
     const uint64_t my_key = agent_key(skey, j, kWolfEatKey);
     uint32_t r = 0;
-    for (int32_t w = int32_t(a.claims[3 * c + 2]); w >= 0; w = a.blist[1][w])
+    for (int32_t w = head_slot(a, a.claims[3 * c + 2]); w >= 0; w = a.blist[1][w])
         r += agent_key(skey, w, kWolfEatKey) < my_key;
-    const int32_t first = int32_t(a.claims[3 * c + 1]);
+    const int32_t first = head_slot(a, a.claims[3 * c + 1]);
     for (int32_t q = first; q >= 0; q = a.blist[0][q]) {
         const uint64_t kq = agent_key(skey, q, kSheepPreyKey);
         uint32_t below = 0;
@@ -383,21 +411,21 @@ __global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
         for (int q = 0; q < kInFlight; ++q) {
             if (!on[q] || c[q] < 0) continue;
             if (s == 0) {
-                if (a.claims[3 * c[q]] == agent_key(skey, i[q], kSheepGrassKey)) {
+                if (a.claims[3 * c[q]] == claim_key(a, skey, i[q], kSheepGrassKey)) {
                     e[q] += a.gain_s;
                     sp.e[i[q]] = e[q];
                     a.ready[c[q]] = int32_t(a.step + uint32_t(a.R));
                     ++grass_eaten;
                 }
                 if (!a.multi)
-                    eaten[q] = a.claims[3 * c[q] + 2] != kNoClaim &&
-                               a.claims[3 * c[q] + 1] == agent_key(skey, i[q], kSheepPreyKey);
+                    eaten[q] = claimed(a, a.claims[3 * c[q] + 2]) &&
+                               a.claims[3 * c[q] + 1] == claim_key(a, skey, i[q], kSheepPreyKey);
                 if (eaten[q]) {
                     if (!a.multi) sp.alive[i[q]] = 2;
                     ++sheep_eaten;
                 }
-            } else if (!a.multi && a.claims[3 * c[q] + 1] != kNoClaim &&
-                       a.claims[3 * c[q] + 2] == agent_key(skey, i[q], kWolfEatKey)) {
+            } else if (!a.multi && claimed(a, a.claims[3 * c[q] + 1]) &&
+                       a.claims[3 * c[q] + 2] == claim_key(a, skey, i[q], kWolfEatKey)) {
                 // (multi_prey: K1b has already added the gain)
                 e[q] += a.gain_w;
                 sp.e[i[q]] = e[q];
@@ -442,11 +470,10 @@ __global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
     const uint32_t mask = a.bits[s][wi];          // live at K1, eaten sheep included
     uint32_t first;
     const uint32_t n = block_list(mask, list, wl, &first);
-    // this workgroup's slice of the claim tables is re-armed for the next
-    // step (K2, the last reader, has finished): whole lines, streamed, which
-    // measured faster than each agent resetting the words it posted (scattered
-    // 8-byte stores, each a read-modify-write at the memory)
-    {
+    // at the end of a tag period this workgroup's slice of the claim tables is
+    // re-armed for the next step (K2, the last reader, has finished): whole
+    // lines, streamed
+    if (a.rearm) {
         const int64_t words = 3 * a.G, per = (words + gridDim.x - 1) / gridDim.x;
         const int64_t lo = int64_t(blockIdx.x) * per;
         const int64_t hi = lo + per < words ? lo + per : words;
@@ -717,6 +744,19 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.multi = p->multi_prey;
     a.step = s->step;
     a.stats = nullptr;
+    // claim keys (claim_key): slots below 2^sb, a tag of up to kTagBits bits
+    // sb + 32 bits up; a period of steps uses the tags t_max - 1 down to 1 (tag
+    // 0 every step when only one tag bit is left), and its last step re-arms
+    // the table.  Short periods re-arm often enough to cost little (one
+    // streamed table per 14 steps) and keep every multi-step call crossing them.
+    const int64_t max_cap = p->cap_s > p->cap_w ? p->cap_s : p->cap_w;
+    uint32_t sb = 1;
+    while (sb < 31 && (int64_t(1) << sb) < max_cap) ++sb;
+    const uint32_t tag_bits = 32 - sb < kTagBits ? 32 - sb : kTagBits;
+    const uint64_t t_max = (uint64_t(1) << tag_bits) - 1;
+    const uint64_t period = t_max > 1 ? t_max - 1 : 1;
+    a.sb = sb;
+    a.tag_mask = ~uint64_t(0) << (32 + sb);
 
     const int64_t words_s = int64_t(a.tiles[0]) * kBlock, words_w = int64_t(a.tiles[1]) * kBlock;
     int64_t edge = G > words_s ? G : words_s;
@@ -734,6 +774,9 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     for (int32_t k = 0; k < n_steps; ++k) {
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
+        const uint64_t phase = uint64_t(k) % period;
+        a.tag_hi = ((t_max > 1 ? t_max - 1 : 0) - phase) << (32 + sb);
+        a.rearm = phase == period - 1;
         hipLaunchKernelGGL(k_move_claim, tile_grid, dim3(kBlock), 0, st, a);
         if (a.multi)
             hipLaunchKernelGGL(k_prey_match, dim3(static_cast<uint32_t>(tiles_for(p->cap_w, kBlock))),
