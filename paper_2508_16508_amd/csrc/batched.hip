@@ -19,12 +19,14 @@
 //                      lists of their cell instead of posting prey and eater
 //                      keys, and a pass between A and B pairs each cell's
 //                      wolves and sheep by rank; see prey_match)
-//   C  re-arm + breed  every agent that was live at the start of the step
-//                      resets the claim words it posted (so the tables return
-//                      to all-ones after touching only occupied cells), then
-//                      free slots (alive 0 or 2) are ranked, the free slot of
+//   C  breed           free slots (alive 0 or 2) are ranked, the free slot of
 //                      rank j < #breeders pulls its child from breeder j, and
 //                      live agents with negative energy die.
+// Claim keys carry a step tag (see tagged_key): within a period of steps a
+// word left by an earlier step reads as unclaimed and loses to every fresh
+// key, so the model's claim table is re-armed (streamed back to all-ones) only
+// in pass C of a period's last step and of the last step a launch runs, which
+// keeps the tables all-ones between launches.
 // A model run by one workgroup whose claim table (three words per cell) fits
 // in the workgroup's dynamic LDS keeps it there (LOCAL): the table is set to
 // all-ones when the model is taken, pass A posts into it with LDS atomics, and
@@ -47,6 +49,7 @@ namespace abm {
 namespace {
 
 constexpr uint64_t kNoClaim = ~0ull;
+constexpr uint32_t kTagBits = 4;     // claim-key tag: periods of 14 steps
 constexpr uint32_t kDxPacked = 0x9224u;  // see predation.hip: dir -> dx + 1, 2 bits each
 constexpr uint32_t kDyPacked = 0xA940u;
 
@@ -95,15 +98,15 @@ __device__ __forceinline__ void claim_min_lds(uint64_t* p, uint64_t key) {
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Pushes slot onto the list whose head is *p; returns the previous head.
-__device__ __forceinline__ uint64_t push_head(uint64_t* p, int32_t slot) {
-    return __hip_atomic_exchange(p, uint64_t(uint32_t(slot)), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
+// Makes `word` (a slot with the step's tag) the head of the list whose head
+// is *p; returns the previous head.
+__device__ __forceinline__ uint64_t push_head(uint64_t* p, uint64_t word) {
+    return __hip_atomic_exchange(p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t push_head_lds(uint64_t* p, int32_t slot) {
+__device__ __forceinline__ uint64_t push_head_lds(uint64_t* p, uint64_t word) {
     typedef __attribute__((address_space(3))) unsigned long long lds_u64;
-    return __hip_atomic_exchange((lds_u64*)p, static_cast<unsigned long long>(uint32_t(slot)),
+    return __hip_atomic_exchange((lds_u64*)p, static_cast<unsigned long long>(word),
                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -121,6 +124,15 @@ __device__ __forceinline__ void local_fill(uint64_t* lc, int32_t words) {
     for (int32_t i = threadIdx.x; i < words; i += blockDim.x) lc[i] = kNoClaim;
 }
 
+// (tag, draw, slot) from the high bits down: within a step these order as
+// (draw, slot), the method's claim order; an earlier step of the period has
+// a larger tag, so its words lose to fresh keys and read as unclaimed.
+__device__ __forceinline__ uint64_t tagged_key(uint64_t tag_hi, uint32_t sb, uint64_t skey,
+                                               int64_t slot, uint32_t purpose) {
+    return tag_hi | (uint64_t(draw(skey, uint32_t(slot), purpose)) << sb) | uint64_t(slot);
+}
+
+// The ranking order of multi-prey (no tag: only keys of one step are compared).
 __device__ __forceinline__ uint64_t key_of(uint64_t skey, int64_t slot, uint32_t purpose) {
     return (uint64_t(draw(skey, uint32_t(slot), purpose)) << 32) | uint32_t(slot);
 }
@@ -192,6 +204,10 @@ struct ModelView {
     int32_t W, H, R, gain[2];
     uint32_t T[2], seed;
     bool multi;                  // prey matched by rank within a cell
+    uint32_t sb;                 // slot bits of a claim key
+    uint32_t period;             // steps per tag period
+    uint64_t tag_top;            // the first tag of a period
+    uint64_t tag_mask;           // the tag field and the bits above it
     int32_t cap[2];
     int32_t* link[2];            // list links (multi), per species
     int32_t* ready;
@@ -276,14 +292,14 @@ __device__ __forceinline__ bool team_sync(Team& tm) {
 // lists, whose heads are the prey (sheep) and eater (wolf) words; distinct
 // wolves have distinct ranks, so no sheep is taken twice.  Quadratic in the
 // sheep of one cell, which are few at the workloads' densities.
-template <class Read>
+template <class Read, class Head>
 __device__ __forceinline__ void prey_match(const ModelView& v, uint64_t skey, const uint64_t* cw,
-                                           int32_t j, Read rd) {
-    const int32_t first = int32_t(uint32_t(rd(cw + 1)));
+                                           int32_t j, Read rd, Head head) {
+    const int32_t first = head(rd(cw + 1));
     if (first < 0) return;
     const uint64_t mine = key_of(skey, j, kWolfEatKey);
     uint32_t r = 0;
-    for (int32_t w = int32_t(uint32_t(rd(cw + 2))); w >= 0; w = v.link[1][w])
+    for (int32_t w = head(rd(cw + 2)); w >= 0; w = v.link[1][w])
         r += key_of(skey, w, kWolfEatKey) < mine ? 1u : 0u;
     for (int32_t q = first; q >= 0; q = v.link[0][q]) {
         const uint64_t kq = key_of(skey, q, kSheepPreyKey);
@@ -303,8 +319,8 @@ __device__ __forceinline__ void prey_match(const ModelView& v, uint64_t skey, co
 // c0 + (w * ITEMS + k) * 64 + l, so each load instruction of a wave covers 64
 // consecutive slots and the ITEMS loads of a lane are issued together.
 template <int ITEMS, bool LOCAL>
-__device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* lds,
-                           uint32_t* live_out) {
+__device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool last, Team& tm,
+                           uint32_t* lds, uint32_t* live_out) {
     uint64_t* const claims = LOCAL ? local_claims() : v.claims;
     // LOCAL: the atomics of pass A are complete at the barrier that ends it
     auto rd = [](const uint64_t* p) { return LOCAL ? *p : ld_claim(p); };
@@ -314,10 +330,23 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
         else
             claim_min(p, key);
     };
-    // multi-prey: the agent's link is the cell's previous head (kNoClaim: -1, the end)
-    auto push = [](uint64_t* p, int32_t slot, int32_t* link) {
-        const uint64_t prev = LOCAL ? push_head_lds(p, slot) : push_head(p, slot);
-        link[slot] = int32_t(uint32_t(prev));
+    // wave-uniform: kept in scalar registers
+    const uint32_t phase = __builtin_amdgcn_readfirstlane((t - t0) % v.period);
+    const uint32_t sb = __builtin_amdgcn_readfirstlane(v.sb);
+    const uint64_t tag_hi =
+        uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v.tag_top - phase) << sb)) << 32;
+    const uint64_t tag_mask =
+        uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v.tag_mask >> 32))) << 32;
+    auto claimed = [tag_hi, tag_mask](uint64_t w) { return (w & tag_mask) == tag_hi; };
+    // a list head's slot, or -1 (a word of an earlier step, or all-ones: the end)
+    auto head = [tag_hi, tag_mask](uint64_t w) {
+        return (w & tag_mask) == tag_hi ? int32_t(w & ~tag_mask) : -1;
+    };
+    // multi-prey: the agent's link is the cell's previous head
+    auto push = [tag_hi, head](uint64_t* p, int32_t slot, int32_t* link) {
+        const uint64_t word = tag_hi | uint64_t(uint32_t(slot));
+        const uint64_t prev = LOCAL ? push_head_lds(p, word) : push_head(p, word);
+        link[slot] = head(prev);
     };
     const uint64_t skey = stream_key(v.seed, t);
     const uint32_t move_p[2] = {kSheepMove, kWolfMove};
@@ -370,15 +399,16 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                 const int64_t c = int64_t(y) * v.W + x;
                 uint64_t* cw = claims + 3 * c;
                 if (s == 0) {
-                    if (v.ready[c] <= int32_t(t)) post(cw + 0, key_of(skey, i, kSheepGrassKey));
+                    if (v.ready[c] <= int32_t(t))
+                        post(cw + 0, tagged_key(tag_hi, sb, skey, i, kSheepGrassKey));
                     if (v.multi)
                         push(cw + 1, i, v.link[0]);
                     else
-                        post(cw + 1, key_of(skey, i, kSheepPreyKey));
+                        post(cw + 1, tagged_key(tag_hi, sb, skey, i, kSheepPreyKey));
                 } else if (v.multi) {
                     push(cw + 2, i, v.link[1]);
                 } else {
-                    post(cw + 2, key_of(skey, i, kWolfEatKey));
+                    post(cw + 2, tagged_key(tag_hi, sb, skey, i, kWolfEatKey));
                 }
             }
         }
@@ -395,7 +425,7 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                 if (j >= hi[1] || v.al[1][j] == 0) continue;
                 const int32_t x = v.x[1][j], y = v.y[1][j];
                 if (!on_grid(v, x, y)) continue;
-                prey_match(v, skey, claims + 3 * (int64_t(y) * v.W + x), j, rd);
+                prey_match(v, skey, claims + 3 * (int64_t(y) * v.W + x), j, rd, head);
             }
         }
         if (!team_sync(tm)) return false;   // eaten sheep and wolves' gains are visible
@@ -428,21 +458,21 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
                     const int64_t c = int64_t(y) * v.W + x;
                     const uint64_t* cw = claims + 3 * c;
                     if (s == 0) {
-                        if (rd(cw + 0) == key_of(skey, i, kSheepGrassKey)) {
+                        if (rd(cw + 0) == tagged_key(tag_hi, sb, skey, i, kSheepGrassKey)) {
                             e += v.gain[0];
                             v.e[0][i] = e;
                             v.ready[c] = int32_t(t) + v.R;
                         }
                         if (v.multi) {
                             eaten = al[k] == 2;   // taken by a wolf of its cell
-                        } else if (rd(cw + 2) != kNoClaim &&
-                                   rd(cw + 1) == key_of(skey, i, kSheepPreyKey)) {
+                        } else if (claimed(rd(cw + 2)) &&
+                                   rd(cw + 1) == tagged_key(tag_hi, sb, skey, i, kSheepPreyKey)) {
                             v.al[0][i] = 2;   // eaten: dead, its claims still to be reset
                             eaten = true;
                         }
                         nfree += eaten ? 1u : 0u;
-                    } else if (!v.multi && rd(cw + 1) != kNoClaim &&
-                               rd(cw + 2) == key_of(skey, i, kWolfEatKey)) {
+                    } else if (!v.multi && claimed(rd(cw + 1)) &&
+                               rd(cw + 2) == tagged_key(tag_hi, sb, skey, i, kWolfEatKey)) {
                         e += v.gain[1];
                         v.e[1][i] = e;
                     }
@@ -509,9 +539,17 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
     }
     *live_out = uint32_t(fpre[2]);
 
-    // ---- C: re-arm claims, breed into free slots, starve
-    // (LOCAL: every read of the table in B is behind the barrier above)
-    if constexpr (LOCAL) local_fill(claims, 3 * v.W * v.H);
+    // ---- C: breed into free slots, starve; re-arm the claims (every read of
+    // the table in B is behind the barrier above): LOCAL every step, else at
+    // the end of a tag period and at the last step of the launch, each team
+    // member its share of the table
+    if constexpr (LOCAL) {
+        local_fill(claims, 3 * v.W * v.H);
+    } else if (phase == v.period - 1 || last) {
+        const int64_t words = 3 * int64_t(v.W) * v.H;
+        const int64_t w0 = words * tm.r / tm.K, w1 = words * (tm.r + 1) / tm.K;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += blockDim.x) rearm(claims + w);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const int32_t* bpre = s ? bpre1 : bpre0;
@@ -530,20 +568,9 @@ __device__ bool model_step(const ModelView& v, uint32_t t, Team& tm, uint32_t* l
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
                 fr[k] = i < hi[s] && (al[k] == 0 || al[k] == 2);
-                if (LOCAL || i >= hi[s] || al[k] == 0) continue;
-                // this agent posted claims in A: reset them
-                const int32_t x = v.x[s][i], y = v.y[s][i];
-                if (!on_grid(v, x, y)) continue;
-                uint64_t* cw = claims + 3 * (int64_t(y) * v.W + x);
-                if (s == 0) {
-                    rearm(cw + 0);
-                    rearm(cw + 1);
-                } else {
-                    rearm(cw + 2);
-                }
             }
             uint32_t rank[ITEMS];
-            const uint32_t tot = chunk_rank<ITEMS>(fr, rank, lds);   // barrier: x/y read first
+            const uint32_t tot = chunk_rank<ITEMS>(fr, rank, lds);
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
@@ -583,6 +610,18 @@ __device__ ModelView view_of(const BatchArgs& a, const abm_model_desc* d) {
     v.T[1] = d->T_w;
     v.seed = d->seed;
     v.multi = d->multi_prey != 0;
+    // claim keys: slots below 2^sb (caps are at most 2^30), a tag of up to
+    // kTagBits bits above the 32-bit draw; tags tag_top down to 1 (0 alone when
+    // one tag bit is left, re-arming every step); all-ones has a tag no step uses
+    const int64_t max_cap = d->cap_s > d->cap_w ? d->cap_s : d->cap_w;
+    uint32_t sb = 1;
+    while (sb < 31 && (int64_t(1) << sb) < max_cap) ++sb;
+    const uint32_t tag_bits = 32 - sb < kTagBits ? 32 - sb : kTagBits;
+    const uint64_t t_max = (uint64_t(1) << tag_bits) - 1;
+    v.sb = sb;
+    v.tag_top = t_max > 1 ? t_max - 1 : 0;
+    v.period = t_max > 1 ? uint32_t(t_max - 1) : 1u;
+    v.tag_mask = ~uint64_t(0) << (32 + sb);
     v.link[0] = a.link_s ? a.link_s + d->sheep_off : nullptr;
     v.link[1] = a.link_w ? a.link_w + d->wolf_off : nullptr;
     v.cap[0] = int32_t(d->cap_s);
@@ -702,8 +741,10 @@ __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds
     }
     for (int32_t t = t0; t < t1; ++t) {
         uint32_t live;
-        const bool ok = local ? model_step<ITEMS, true>(v, uint32_t(t), tm, lds, &live)
-                              : model_step<ITEMS, false>(v, uint32_t(t), tm, lds, &live);
+        const bool last = t + 1 == t1;
+        const bool ok =
+            local ? model_step<ITEMS, true>(v, uint32_t(t), uint32_t(t0), last, tm, lds, &live)
+                  : model_step<ITEMS, false>(v, uint32_t(t), uint32_t(t0), last, tm, lds, &live);
         if (!ok) return false;
         updates += live;
     }
