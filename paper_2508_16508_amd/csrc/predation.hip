@@ -6,10 +6,10 @@
 // again (grown at step t iff ready <= t), so no per-step regrow pass is needed,
 // and a bitmask in the workspace marks the live slots, so the per-step kernels
 // read 1 bit per slot instead of the 4-byte alive word and visit only live
-// agents.  Each kernel works on tiles of 8192 slots (256 threads, thread t
-// owning the 32 slots of bitmask word t); a tile first compacts its live slots
-// into a list in LDS and then spreads that list over all its threads, four
-// agents per thread in flight, so dense and sparse tiles alike keep every
+// agents.  Each kernel works on tiles of 8192 slots (512 threads, thread t <
+// 256 owning the 32 slots of bitmask word t); a tile first compacts its live
+// slots into a list in LDS and then spreads that list over all its threads,
+// four agents per thread in flight, so dense and sparse tiles alike keep every
 // lane busy.  Step t is three launches (each arrow a grid-wide dependency):
 //   K1 move+claim   every live agent moves, pays 1 energy and posts its
 //                   packed (step tag, draw, slot) key with a 64-bit atomicMin
@@ -53,7 +53,13 @@ constexpr uint32_t kTagBits = 4;                  // claim-key tag: periods of 1
 #ifndef ABM_PRED_IN_FLIGHT
 #define ABM_PRED_IN_FLIGHT 4
 #endif
-constexpr int kInFlight = ABM_PRED_IN_FLIGHT;      // list entries per thread and batch
+constexpr int kInFlight = ABM_PRED_IN_FLIGHT;
+// Threads per tile: kBlock own the tile's bitmask words, and kHelpers times
+// as many share the tile's list of agents.  Live agents crowd the low tiles
+// (children take the lowest free slots), so a few hundred tiles hold all the
+// work; twice the threads on each measured 9% less time per step at 2048^2
+// (four times: slower, the idle tiles then need more dispatch rounds).
+constexpr int kHelpers = 2;      // list entries per thread and batch
 constexpr uint64_t kNoClaim = ~0ull;
 
 // Offsets of the eight neighbours, indexed by dir = draw >> 29, packed as
@@ -237,6 +243,7 @@ __device__ __forceinline__ TileRef tile_of(const StepArgs& a) {
 // length (the same in every thread); *first receives the list index of this
 // thread's first set bit.  Contains three block barriers; the list is
 // complete when it returns.
+template <int WAVES = kWaves>
 __device__ __forceinline__ uint32_t block_list(uint32_t mask, uint16_t* list, uint32_t* wl,
                                                uint32_t* first) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -253,7 +260,7 @@ __device__ __forceinline__ uint32_t block_list(uint32_t mask, uint16_t* list, ui
     __syncthreads();
     uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
         const uint32_t v = wl[w];
         before += w < wave ? v : 0u;
         total += v;
@@ -286,24 +293,27 @@ __device__ __forceinline__ bool grown(int32_t ready, uint32_t step) {
 }
 
 // ------------------------------------------------------------------ K1
-__global__ __launch_bounds__(kBlock) void k_move_claim(StepArgs a) {
+template <int H>
+__global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
+    constexpr int kThreads = kBlock * H;
     __shared__ uint16_t list[kTile];
-    __shared__ uint32_t wl[kWaves];
-    __shared__ uint32_t lds[kWaves];
+    __shared__ uint32_t wl[kWaves * H];
+    __shared__ uint32_t lds[kWaves * H];
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
-    const uint32_t mask = a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x];
+    const uint32_t mask =
+        threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     uint32_t first;
-    const uint32_t n = block_list(mask, list, wl, &first);
+    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     const uint64_t skey = stream_key(a.seed, a.step);
-    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kThreads) {
         int64_t i[kInFlight], c[kInFlight];
         int32_t x[kInFlight], y[kInFlight];
         bool on[kInFlight];
 #pragma unroll
         for (int q = 0; q < kInFlight; ++q) {
-            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            const uint32_t j = j0 + uint32_t(q * kThreads) + threadIdx.x;
             on[q] = j < n;
             i[q] = t.base + (on[q] ? list[j] : 0);
             if (on[q]) {
@@ -381,26 +391,31 @@ __global__ __launch_bounds__(kBlock) void k_prey_match(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ K2
-__global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
+// H x kBlock threads: threads below kBlock own the tile's bitmask words, all
+// of them take part in the tile's list of agents (as in K1 and K3).
+template <int H>
+__global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
+    constexpr int kThreads = kBlock * H;
     __shared__ uint16_t list[kTile];
-    __shared__ uint32_t wl[kWaves];
-    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t wl[kWaves * H];
+    __shared__ uint32_t lds[kWaves * H + 1];
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
     const uint32_t epoch = read_epoch(a.epoch);
-    const uint32_t mask = a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x];
+    const uint32_t mask =
+        threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     uint32_t first;
-    const uint32_t n = block_list(mask, list, wl, &first);
+    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     const uint64_t skey = stream_key(a.seed, a.step);
     uint32_t grass_eaten = 0, sheep_eaten = 0;
-    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kThreads) {
         int64_t i[kInFlight], c[kInFlight];
         int32_t e[kInFlight];
         bool on[kInFlight], eaten[kInFlight];
 #pragma unroll
         for (int q = 0; q < kInFlight; ++q) {
-            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            const uint32_t j = j0 + uint32_t(q * kThreads) + threadIdx.x;
             on[q] = j < n;
             i[q] = t.base + (on[q] ? list[j] : 0);
             c[q] = on[q] ? cell_of(sp.x[i[q]], sp.y[i[q]], a.W, a.H) : -1;
@@ -437,13 +452,13 @@ __global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
             const bool br = !eaten[q] && e[q] > 0 &&
                             draw(skey, uint32_t(i[q]), s ? kWolfBreed : kSheepBreed) <
                                 (s ? a.T_w : a.T_s);
-            tag(list, j0 + uint32_t(q * kBlock) + threadIdx.x, br ? 1u : 0u);
+            tag(list, j0 + uint32_t(q * kThreads) + threadIdx.x, br ? 1u : 0u);
         }
     }
     __syncthreads();
     const uint32_t bm = flagged(mask, first, list, 1);
     uint32_t r0, total;
-    const uint32_t tile_excl = rank_counts<kWaves>(__popc(bm), &r0, a.status + a.chain_off[s],
+    const uint32_t tile_excl = rank_counts<kWaves * H>(__popc(bm), &r0, a.status + a.chain_off[s],
                                                    a.status - 1, t.tile, a.tiles[s], epoch, lds,
                                                    &total);
     uint32_t r = tile_excl + r0;
@@ -457,19 +472,22 @@ __global__ __launch_bounds__(kBlock) void k_eat_breeders(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ K3
-__global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
+template <int H>
+__global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
+    constexpr int kThreads = kBlock * H;
     __shared__ uint16_t list[kTile];
-    __shared__ uint32_t wl[kWaves];
-    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t wl[kWaves * H];
+    __shared__ uint32_t lds[kWaves * H + 1];
+    const bool owner = threadIdx.x < kBlock;      // owns bitmask word threadIdx.x
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
     const uint32_t epoch = read_epoch(a.epoch);
     const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t wi = int64_t(t.tile) * kBlock + threadIdx.x;
-    const uint32_t mask = a.bits[s][wi];          // live at K1, eaten sheep included
+    const uint32_t mask = owner ? a.bits[s][wi] : 0u;   // live at K1, eaten sheep included
     uint32_t first;
-    const uint32_t n = block_list(mask, list, wl, &first);
+    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     // at the end of a tag period this workgroup's slice of the claim tables is
     // re-armed for the next step (K2, the last reader, has finished): whole
     // lines, streamed
@@ -477,17 +495,17 @@ __global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
         const int64_t words = 3 * a.G, per = (words + gridDim.x - 1) / gridDim.x;
         const int64_t lo = int64_t(blockIdx.x) * per;
         const int64_t hi = lo + per < words ? lo + per : words;
-        for (int64_t w = lo + threadIdx.x; w < hi; w += kBlock) a.claims[w] = kNoClaim;
+        for (int64_t w = lo + threadIdx.x; w < hi; w += kThreads) a.claims[w] = kNoClaim;
     }
     // eaten sheep become free slots, starving agents die
     uint32_t starved = 0;
-    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kBlock) {
+    for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kThreads) {
         int64_t i[kInFlight];
         int32_t al[kInFlight], e[kInFlight];
         bool on[kInFlight];
 #pragma unroll
         for (int q = 0; q < kInFlight; ++q) {
-            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            const uint32_t j = j0 + uint32_t(q * kThreads) + threadIdx.x;
             on[q] = j < n;
             i[q] = t.base + (on[q] ? list[j] : 0);
             al[q] = on[q] ? sp.alive[i[q]] : 0;
@@ -506,17 +524,18 @@ __global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
                 sp.alive[i[q]] = 0;
                 ++starved;
             }
-            tag(list, j0 + uint32_t(q * kBlock) + threadIdx.x, f);
+            tag(list, j0 + uint32_t(q * kThreads) + threadIdx.x, f);
         }
     }
     __syncthreads();
     const uint32_t eaten_m = flagged(mask, first, list, 1);
     const uint32_t starved_m = flagged(mask, first, list, 2);
     const int64_t lane0 = t.base + int64_t(threadIdx.x) * 32;
-    const uint32_t in_cap = lane0 >= cap ? 0u : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
+    const uint32_t in_cap = !owner || lane0 >= cap ? 0u
+                          : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
     const uint32_t free_m = ((~mask) & in_cap) | eaten_m;
     uint32_t r0, total;
-    const uint32_t tile_excl = rank_counts<kWaves>(__popc(free_m), &r0, a.status + a.chain_off[s],
+    const uint32_t tile_excl = rank_counts<kWaves * H>(__popc(free_m), &r0, a.status + a.chain_off[s],
                                                    a.status - 1, t.tile, a.tiles[s], epoch, lds,
                                                    &total);
     const int64_t nb = *a.d_nb[s];
@@ -529,17 +548,17 @@ __global__ __launch_bounds__(kBlock) void k_breed_die(StepArgs a) {
         uint32_t m = free_m;
         for (uint32_t k = 0; k < mine && m; ++k, m &= m - 1u) born_m |= m & (0u - m);
     }
-    a.bits[s][wi] = (mask & ~eaten_m & ~starved_m) | born_m;
+    if (owner) a.bits[s][wi] = (mask & ~eaten_m & ~starved_m) | born_m;
     // the children, spread over the block: list the free slots that receive one
     uint32_t bfirst;
-    const uint32_t nborn = block_list(born_m, list, wl, &bfirst);
-    for (uint32_t j0 = 0; j0 < nborn; j0 += kInFlight * kBlock) {
+    const uint32_t nborn = block_list<kWaves * H>(born_m, list, wl, &bfirst);
+    for (uint32_t j0 = 0; j0 < nborn; j0 += kInFlight * kThreads) {
         int64_t ci[kInFlight], p[kInFlight];
         int32_t px[kInFlight], py[kInFlight], pe[kInFlight];
         bool on[kInFlight];
 #pragma unroll
         for (int q = 0; q < kInFlight; ++q) {
-            const uint32_t j = j0 + uint32_t(q * kBlock) + threadIdx.x;
+            const uint32_t j = j0 + uint32_t(q * kThreads) + threadIdx.x;
             on[q] = j < nborn;
             ci[q] = t.base + (on[q] ? list[j] : 0);
             p[q] = on[q] ? a.blist[s][tile_excl + j] : 0;
@@ -777,16 +796,16 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         const uint64_t phase = uint64_t(k) % period;
         a.tag_hi = ((t_max > 1 ? t_max - 1 : 0) - phase) << (32 + sb);
         a.rearm = phase == period - 1;
-        hipLaunchKernelGGL(k_move_claim, tile_grid, dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_move_claim<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
         if (a.multi)
             hipLaunchKernelGGL(k_prey_match, dim3(static_cast<uint32_t>(tiles_for(p->cap_w, kBlock))),
                                dim3(kBlock), 0, st, a);
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
-        hipLaunchKernelGGL(k_eat_breeders, tile_grid, dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_eat_breeders<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
-        hipLaunchKernelGGL(k_breed_die, tile_grid, dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_breed_die<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
         if (a.stats) hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, st, w.acc, a.stats);
     }
     hipLaunchKernelGGL(k_call_end, dim3(static_cast<uint32_t>(tiles_for(G, kBlock))), dim3(kBlock),
