@@ -59,7 +59,12 @@ constexpr int kInFlight = ABM_PRED_IN_FLIGHT;
 // (children take the lowest free slots), so a few hundred tiles hold all the
 // work; twice the threads on each measured 9% less time per step at 2048^2
 // (four times: slower, the idle tiles then need more dispatch rounds).
-constexpr int kHelpers = 2;      // list entries per thread and batch
+constexpr int kHelpers = 2;
+// header words of the free-slot totals (words 4 and 5 are unused by the
+// common layout)
+constexpr int kHdrFreeA = 4, kHdrFreeB = 5;
+static_assert(kHdrFreeA > kHdrCountB && kHdrFreeB < kHdrError, "header word clash");
+static_assert(kWaves * kHelpers >= 2 * kLevels, "the dual-chain prefix needs 2 kLevels waves");      // list entries per thread and batch
 constexpr uint64_t kNoClaim = ~0ull;
 
 // Offsets of the eight neighbours, indexed by dir = draw >> 29, packed as
@@ -101,8 +106,11 @@ struct StepArgs {
     EpochArg epoch;
     int32_t* blist[2];    // breeder lists
     int64_t* d_nb[2];     // breeder counts
+    int64_t* d_nf[2];     // free-slot counts (this step's births are min(nf, nb))
+    int32_t* free_pre[2]; // per tile: exclusive free-slot prefix, written by K2 for K3
     uint32_t tiles[2];
-    uint32_t chain_off[2];  // start of each species' scan chain in the status words
+    uint32_t chain_off[2];  // start of each species' breeder scan chain in the status words
+    uint32_t fchain_off[2]; // ... and of its free-slot scan chain
     int32_t multi;          // prey by rank within a cell (K1 builds lists, K1b matches)
 };
 
@@ -292,6 +300,84 @@ __device__ __forceinline__ bool grown(int32_t ready, uint32_t step) {
     return int32_t(uint32_t(ready) - step) <= 0;
 }
 
+// Tile-local part of a rank: this thread's exclusive rank of its count c
+// (0 <= c < 64) in thread order, and the tile total.  lds holds one word per
+// wave.  Two block barriers.
+template <int WAVES>
+__device__ __forceinline__ uint32_t rank_block(uint32_t c, uint32_t* thread_excl, uint32_t* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t excl = 0, wtot = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const uint64_t bal = __ballot((c >> b) & 1u);
+        excl += lane_rank(bal) << b;
+        wtot += static_cast<uint32_t>(__popcll(bal)) << b;
+    }
+    __syncthreads();
+    if (lane == 0) lds[wave] = wtot;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        const uint32_t v = lds[w];
+        before += w < wave ? v : 0u;
+        total += v;
+    }
+    *thread_excl = before + excl;
+    return total;
+}
+
+// Exclusive prefixes of two counts of this tile over two chains at once (the
+// hierarchical look-back of the single-pass scan, one chain per group of
+// kLevels waves: waves 0-3 walk chain A with count a, waves 4-7 chain B with
+// count b).  Needs 2 kLevels waves; lds holds 2 kLevels words.  Two barriers.
+__device__ __forceinline__ void hier_prefix2(uint64_t* chain_a, uint64_t* chain_b, uint64_t* err,
+                                             uint32_t t, uint32_t T, uint32_t epoch, uint32_t a,
+                                             uint32_t b, uint32_t* lds, uint32_t* pre_a,
+                                             uint32_t* pre_b) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const bool second = wave >= kLevels;
+    const int lv = second ? wave - kLevels : wave;
+    const uint32_t count = second ? b : a;
+    uint32_t part = 0;
+    if (wave < 2 * kLevels) {
+        uint64_t* level = second ? chain_b : chain_a;
+        uint32_t n = T;
+        for (int l = 0; l < lv; ++l) {
+            level += n;
+            n = (n + 63) >> 6;
+        }
+        const uint32_t g = t >> (6 * lv);
+        const uint32_t d = g & 63u;
+        const uint32_t pspan = 1u << (6 * (lv + 1));
+        const bool publish = (((t & (pspan - 1)) == pspan - 1) || t == T - 1) && lv + 1 < kLevels;
+        if (lv == 0 && lane == 0) st_agent(&level[g], pack_status(epoch, kFlagAgg, count));
+        uint32_t v = 0;
+        if (lane < d || (lane == d && lv > 0 && publish)) {
+            const uint32_t idx = g - d + lane;
+            v = static_cast<uint32_t>(poll_status(&level[idx], ld_agent(&level[idx]), epoch, err));
+        }
+        const uint32_t own = (lv == 0) ? count : 0u;
+        part = wave_sum(lane < d ? v : 0u);
+        if (publish) {
+            const uint32_t incl = wave_sum(v) + own;
+            if (lane == 0) st_agent(&(level + n)[g >> 6], pack_status(epoch, kFlagAgg, incl));
+        }
+    }
+    __syncthreads();
+    if (lane == 0 && wave < 2 * kLevels) lds[wave] = part;
+    __syncthreads();
+    uint32_t ta = 0, tb = 0;
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) {
+        ta += lds[l];
+        tb += lds[kLevels + l];
+    }
+    *pre_a = ta;
+    *pre_b = tb;
+}
+
 // ------------------------------------------------------------------ K1
 template <int H>
 __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
@@ -398,7 +484,7 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
     constexpr int kThreads = kBlock * H;
     __shared__ uint16_t list[kTile];
     __shared__ uint32_t wl[kWaves * H];
-    __shared__ uint32_t lds[kWaves * H + 1];
+    __shared__ uint32_t lds[2 * kWaves * H + 1];
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
@@ -452,19 +538,35 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
             const bool br = !eaten[q] && e[q] > 0 &&
                             draw(skey, uint32_t(i[q]), s ? kWolfBreed : kSheepBreed) <
                                 (s ? a.T_w : a.T_s);
-            tag(list, j0 + uint32_t(q * kThreads) + threadIdx.x, br ? 1u : 0u);
+            // 1: breeder, 2: eaten (its slot is free for this step's births)
+            tag(list, j0 + uint32_t(q * kThreads) + threadIdx.x, br ? 1u : (eaten[q] ? 2u : 0u));
         }
     }
     __syncthreads();
+    // breeders (compacted in slot order for K3) and the slots free for this
+    // step's births (empty, or eaten this step), ranked over two chains at once
+    const bool owner = threadIdx.x < kBlock;
     const uint32_t bm = flagged(mask, first, list, 1);
-    uint32_t r0, total;
-    const uint32_t tile_excl = rank_counts<kWaves * H>(__popc(bm), &r0, a.status + a.chain_off[s],
-                                                   a.status - 1, t.tile, a.tiles[s], epoch, lds,
-                                                   &total);
+    const uint32_t eaten_m = flagged(mask, first, list, 2);
+    const int64_t cap = s ? a.cap_w : a.cap_s;
+    const int64_t lane0 = t.base + int64_t(threadIdx.x) * 32;
+    const uint32_t in_cap = !owner || lane0 >= cap ? 0u
+                          : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
+    const uint32_t free_m = ((~mask) & in_cap) | eaten_m;
+    uint32_t r0, rf;
+    const uint32_t total = rank_block<kWaves * H>(__popc(bm), &r0, lds);
+    const uint32_t total_f = rank_block<kWaves * H>(__popc(free_m), &rf, lds + kWaves * H);
+    uint32_t tile_excl, free_excl;
+    hier_prefix2(a.status + a.chain_off[s], a.status + a.fchain_off[s], a.status - 1, t.tile,
+                 a.tiles[s], epoch, total, total_f, lds, &tile_excl, &free_excl);
     uint32_t r = tile_excl + r0;
     for (uint32_t m = bm; m; m &= m - 1u)
         a.blist[s][r++] = int32_t(t.base + threadIdx.x * 32u + (__ffs(m) - 1));
-    if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) *a.d_nb[s] = int64_t(tile_excl) + total;
+    if (threadIdx.x == 0) a.free_pre[s][t.tile] = int32_t(free_excl);
+    if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
+        *a.d_nb[s] = int64_t(tile_excl) + total;
+        *a.d_nf[s] = int64_t(free_excl) + total_f;
+    }
     if (a.stats && s == 0) {
         block_add(grass_eaten, a.acc, kGrassEaten, lds);
         block_add(sheep_eaten, a.acc, kSheepEaten, lds);
@@ -482,7 +584,6 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
-    const uint32_t epoch = read_epoch(a.epoch);
     const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t wi = int64_t(t.tile) * kBlock + threadIdx.x;
     const uint32_t mask = owner ? a.bits[s][wi] : 0u;   // live at K1, eaten sheep included
@@ -534,10 +635,10 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     const uint32_t in_cap = !owner || lane0 >= cap ? 0u
                           : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
     const uint32_t free_m = ((~mask) & in_cap) | eaten_m;
-    uint32_t r0, total;
-    const uint32_t tile_excl = rank_counts<kWaves * H>(__popc(free_m), &r0, a.status + a.chain_off[s],
-                                                   a.status - 1, t.tile, a.tiles[s], epoch, lds,
-                                                   &total);
+    // (the same free slots K2 ranked: its chain gave this tile's prefix)
+    uint32_t r0;
+    const uint32_t total = rank_block<kWaves * H>(__popc(free_m), &r0, lds);
+    const uint32_t tile_excl = uint32_t(a.free_pre[s][t.tile]);
     const int64_t nb = *a.d_nb[s];
     const int64_t room = nb - int64_t(tile_excl);
     const uint32_t births = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
@@ -581,7 +682,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     }
     if (a.stats) {
         if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
-            const int64_t nfree = int64_t(tile_excl) + total;
+            const int64_t nfree = *a.d_nf[s];
             a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
         }
         block_add(starved, a.acc, s ? kStarvedW : kStarvedS, lds);
@@ -756,10 +857,23 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.blist[1] = w.list_b;
     a.d_nb[0] = reinterpret_cast<int64_t*>(w.hdr + kHdrCountA);
     a.d_nb[1] = reinterpret_cast<int64_t*>(w.hdr + kHdrCountB);
+    a.d_nf[0] = reinterpret_cast<int64_t*>(w.hdr + kHdrFreeA);
+    a.d_nf[1] = reinterpret_cast<int64_t*>(w.hdr + kHdrFreeB);
     a.tiles[0] = static_cast<uint32_t>(tiles_for(p->cap_s, kTile));
     a.tiles[1] = static_cast<uint32_t>(tiles_for(p->cap_w, kTile));
+    // status words: the breeder chains of both species, then their free-slot
+    // chains, then the per-tile free prefixes (int32) K2 leaves for K3; the
+    // area is sized for 512-slot tiles, 16 times the chains of 8192-slot tiles
+    const int64_t cw0 = chain_words(a.tiles[0]), cw1 = chain_words(a.tiles[1]);
     a.chain_off[0] = 0;
-    a.chain_off[1] = static_cast<uint32_t>(chain_words(a.tiles[0]));
+    a.chain_off[1] = static_cast<uint32_t>(cw0);
+    a.fchain_off[0] = static_cast<uint32_t>(cw0 + cw1);
+    a.fchain_off[1] = static_cast<uint32_t>(2 * cw0 + cw1);
+    const int64_t pre_words = 2 * (cw0 + cw1) + (int64_t(a.tiles[0]) + a.tiles[1] + 1) / 2;
+    if (pre_words > status_words(p->cap_s > p->cap_w ? p->cap_s : p->cap_w))
+        return fail(ABM_E_WORKSPACE, "predation_step: scan state does not fit the workspace");
+    a.free_pre[0] = reinterpret_cast<int32_t*>(w.status + 2 * (cw0 + cw1));
+    a.free_pre[1] = a.free_pre[0] + a.tiles[0];
     a.multi = p->multi_prey;
     a.step = s->step;
     a.stats = nullptr;
@@ -803,8 +917,6 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         rc = next_epoch(w, st, &a.epoch);
         if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_eat_breeders<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
-        rc = next_epoch(w, st, &a.epoch);
-        if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_breed_die<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
         if (a.stats) hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, st, w.acc, a.stats);
     }
