@@ -100,7 +100,10 @@ struct StepArgs {
     uint64_t tag_mask;    // the tag field
     int32_t rearm;        // K3 re-arms the whole table (the tag period ends)
     int64_t* stats;       // this step's row of 8, or null
-    int64_t* acc;         // kAccCounters x kAccLanes spread accumulators
+    int64_t* acc;         // kAccCounters x kAccLanes spread accumulators: per counter, lanes
+                          // [0, 128) for even steps of a call and [128, 256) for odd ones
+    int32_t acc_par;      // this step's half (0 or 128)
+    int64_t* fold_row;    // stats row of the previous step, folded by K1 (or null)
     uint32_t step;
     uint64_t* status;
     EpochArg epoch;
@@ -152,10 +155,12 @@ __device__ __forceinline__ int32_t head_slot(const StepArgs& a, uint64_t word) {
 }
 
 // Block-wide sum of one value per thread, added by thread 0 to this block's
-// lane of the spread accumulator of counter `col` (256 lanes per counter, so
-// no single address takes every block's atomic).
+// lane of the spread accumulator of counter `col` in the step's half (128
+// lanes per counter and step, so no single address takes every block's
+// atomic).  `acc` points at the step's half.
+constexpr int kHalfLanes = kAccLanes / 2;
 __device__ __forceinline__ void block_add(uint32_t v, int64_t* acc, int col, uint32_t* lds) {
-    int64_t* dst = acc + int64_t(col) * kAccLanes + (blockIdx.x & (kAccLanes - 1));
+    int64_t* dst = acc + int64_t(col) * kAccLanes + (blockIdx.x & (kHalfLanes - 1));
     const uint32_t w = wave_sum(v);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = w;
@@ -164,6 +169,23 @@ __device__ __forceinline__ void block_add(uint32_t v, int64_t* acc, int col, uin
         uint32_t s = 0;
         for (int i = 0; i < int(blockDim.x >> 6); ++i) s += lds[i];
         if (s) atomicAdd(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)s);
+    }
+}
+
+// Folds one step's half of the spread accumulators (`acc` points at it)
+// into its stats row (the births columns are written by K3) and clears it for
+// the step after next.  Any number of whole waves.
+__device__ __forceinline__ void fold_stats(int64_t* acc, int64_t* stats) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int col = wave; col < kAccCounters; col += int(blockDim.x >> 6)) {
+        int64_t v = 0;
+        for (int l = lane; l < kHalfLanes; l += 64) {
+            v += acc[col * kAccLanes + l];
+            acc[col * kAccLanes + l] = 0;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0 && col != kBirthsS && col != kBirthsW) stats[col] = v;
     }
 }
 
@@ -388,6 +410,11 @@ __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
     const TileRef t = tile_of(a);
     const int s = t.s;
     const Species sp = a.sp[s];
+    // the previous step's statistics, folded by the last workgroup (a tile
+    // past the live agents, so it has time to spare); this step adds to the
+    // other half of the accumulators
+    if (a.fold_row && blockIdx.x == gridDim.x - 1)
+        fold_stats(a.acc + (kHalfLanes - a.acc_par), a.fold_row);
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     uint32_t first;
@@ -443,7 +470,7 @@ __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
             }
         }
     }
-    if (a.stats) block_add(__popc(mask), a.acc, s ? kLiveW : kLiveS, lds);
+    if (a.stats) block_add(__popc(mask), a.acc + a.acc_par, s ? kLiveW : kLiveS, lds);
 }
 
 // K1b (multi_prey): wolf j of cell c takes rank r among the wolves of c (eat
@@ -568,8 +595,8 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
         *a.d_nf[s] = int64_t(free_excl) + total_f;
     }
     if (a.stats && s == 0) {
-        block_add(grass_eaten, a.acc, kGrassEaten, lds);
-        block_add(sheep_eaten, a.acc, kSheepEaten, lds);
+        block_add(grass_eaten, a.acc + a.acc_par, kGrassEaten, lds);
+        block_add(sheep_eaten, a.acc + a.acc_par, kSheepEaten, lds);
     }
 }
 
@@ -685,7 +712,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
             const int64_t nfree = *a.d_nf[s];
             a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
         }
-        block_add(starved, a.acc, s ? kStarvedW : kStarvedS, lds);
+        block_add(starved, a.acc + a.acc_par, s ? kStarvedW : kStarvedS, lds);
     }
 }
 
@@ -732,20 +759,9 @@ __global__ __launch_bounds__(kBlock) void k_call_end(int32_t* grass, int64_t G, 
     }
 }
 
-// Folds a step's spread accumulators into its stats row (the births columns
-// are written by K3) and clears them for the next step.
+// The last step's fold (every other step's is done by the next step's K1).
 __global__ __launch_bounds__(kBlock) void k_fold_stats(int64_t* acc, int64_t* stats) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int col = wave; col < kAccCounters; col += kBlock / 64) {
-        int64_t v = 0;
-        for (int l = lane; l < kAccLanes; l += 64) {
-            v += acc[col * kAccLanes + l];
-            acc[col * kAccLanes + l] = 0;
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0 && col != kBirthsS && col != kBirthsW) stats[col] = v;
-    }
+    fold_stats(acc, stats);
 }
 
 int check_params(const abm_predation_params* p) {
@@ -877,6 +893,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.multi = p->multi_prey;
     a.step = s->step;
     a.stats = nullptr;
+    a.acc_par = 0;
+    a.fold_row = nullptr;
     // claim keys (claim_key): slots below 2^sb, a tag of up to kTagBits bits
     // sb + 32 bits up; a period of steps uses the tags t_max - 1 down to 1 (tag
     // 0 every step when only one tag bit is left), and its last step re-arms
@@ -907,6 +925,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     for (int32_t k = 0; k < n_steps; ++k) {
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
+        a.acc_par = (k & 1) ? kHalfLanes : 0;
+        a.fold_row = s->stats && k > 0 ? s->stats + 8 * int64_t(k - 1) : nullptr;
         const uint64_t phase = uint64_t(k) % period;
         a.tag_hi = ((t_max > 1 ? t_max - 1 : 0) - phase) << (32 + sb);
         a.rearm = phase == period - 1;
@@ -918,8 +938,9 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         if (rc != ABM_OK) return rc;
         hipLaunchKernelGGL(k_eat_breeders<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
         hipLaunchKernelGGL(k_breed_die<kHelpers>, tile_grid, dim3(kBlock * kHelpers), 0, st, a);
-        if (a.stats) hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, st, w.acc, a.stats);
     }
+    if (s->stats)
+        hipLaunchKernelGGL(k_fold_stats, dim3(1), dim3(kBlock), 0, st, w.acc + a.acc_par, a.stats);
     hipLaunchKernelGGL(k_call_end, dim3(static_cast<uint32_t>(tiles_for(G, kBlock))), dim3(kBlock),
                        0, st, s->grass, G, s->step + uint32_t(n_steps));
     rc = launch_status("predation_step");
