@@ -417,6 +417,7 @@ __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
         fold_stats(a.acc + (kHalfLanes - a.acc_par), a.fold_row);
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
+    if (!__syncthreads_or(mask != 0u)) return;   // no live agent in the tile
     uint32_t first;
     const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     const uint64_t skey = stream_key(a.seed, a.step);
@@ -614,8 +615,6 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t wi = int64_t(t.tile) * kBlock + threadIdx.x;
     const uint32_t mask = owner ? a.bits[s][wi] : 0u;   // live at K1, eaten sheep included
-    uint32_t first;
-    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     // at the end of a tag period this workgroup's slice of the claim tables is
     // re-armed for the next step (K2, the last reader, has finished): whole
     // lines, streamed
@@ -625,6 +624,17 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
         const int64_t hi = lo + per < words ? lo + per : words;
         for (int64_t w = lo + threadIdx.x; w < hi; w += kThreads) a.claims[w] = kNoClaim;
     }
+    const int64_t nb = *a.d_nb[s];
+    if (a.stats && t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
+        const int64_t nfree = *a.d_nf[s];
+        a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
+    }
+    // a tile with no live agent and no birth (its free slots rank past the
+    // breeders) has nothing to do
+    const bool births_here = int64_t(a.free_pre[s][t.tile]) < nb;
+    if (!__syncthreads_or(mask != 0u) && !births_here) return;
+    uint32_t first;
+    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
     // eaten sheep become free slots, starving agents die
     uint32_t starved = 0;
     for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kThreads) {
@@ -666,7 +676,6 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     uint32_t r0;
     const uint32_t total = rank_block<kWaves * H>(__popc(free_m), &r0, lds);
     const uint32_t tile_excl = uint32_t(a.free_pre[s][t.tile]);
-    const int64_t nb = *a.d_nb[s];
     const int64_t room = nb - int64_t(tile_excl);
     const uint32_t births = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
     // this lane's free slots of tile rank < births receive children
@@ -707,13 +716,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
             sp.alive[ci[q]] = 1;
         }
     }
-    if (a.stats) {
-        if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
-            const int64_t nfree = *a.d_nf[s];
-            a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
-        }
-        block_add(starved, a.acc + a.acc_par, s ? kStarvedW : kStarvedS, lds);
-    }
+    if (a.stats) block_add(starved, a.acc + a.acc_par, s ? kStarvedW : kStarvedS, lds);
 }
 
 // ------------------------------------------------------------------ call edges
