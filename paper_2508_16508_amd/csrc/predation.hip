@@ -519,8 +519,9 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
     const uint32_t epoch = read_epoch(a.epoch);
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
-    uint32_t first;
-    const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
+    // (a tile with no live agent skips the list: it still takes part in both scans)
+    uint32_t first = 0, n = 0;
+    if (__syncthreads_or(mask != 0u)) n = block_list<kWaves * H>(mask, list, wl, &first);
     const uint64_t skey = stream_key(a.seed, a.step);
     uint32_t grass_eaten = 0, sheep_eaten = 0;
     for (uint32_t j0 = 0; j0 < n; j0 += kInFlight * kThreads) {
