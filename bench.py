@@ -36,7 +36,7 @@ N_ATTRS = 8
 
 
 LEGS = ("predation_small", "predation_large", "predation_large_multi_prey", "traffic", "lob",
-        "sort_select", "batched", "batched_multi_prey")
+        "sort_select", "batched", "batched_multi_prey", "table1_context")
 
 
 def algorithmic_bytes(op, n, k):
@@ -337,8 +337,49 @@ def batched_leg(abm, W, torch, steps=500, chunk=50, plain_models=32, plain_steps
                        "candidates_ms_per_4_steps": tuning["timings_ms"]}}
 
 
+def table1_context_leg(abm, torch, runs=10):
+    """The paper's Table 1 shapes with the small model's parameters: 100 x 100
+    with 600 sheep + 400 wolves and 1000 x 1000 with 6000 + 4000 (capacities
+    ten times the initial agents), on the one-model path and as the only model
+    of the batched form; 100 steps timed as the paper times them, the median
+    over `runs` fresh models of 105 steps less the median of 5 steps (device
+    events around each run).  Context only: the paper's figures come from other
+    hardware and software."""
+    out = {"method": "median(105 steps) - median(5 steps) over %d fresh models" % runs}
+    for name, side, ns, nw in (("small", 100, 600, 400), ("large", 1000, 6000, 4000)):
+        kw = dict(W=side, H=side, seed=0, cap_s=10 * ns, cap_w=10 * nw, n_s0=ns, n_w0=nw)
+        res = {}
+        for path in ("one_model", "batched"):
+            med = {}
+            for steps in (105, 5):
+                ts = []
+                for r in range(runs):
+                    p = abm.predation_params(**dict(kw, seed=r))
+                    if path == "one_model":
+                        m = abm.predation_init(p)
+                        run = lambda: m.run(steps)
+                    else:
+                        m = abm.BatchedPredation([p], steps, block_threads=1024, items=2)
+                        m.init()
+                        run = lambda: m.run(steps)
+                    torch.cuda.synchronize()
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                    del m
+                med[steps] = _med(ts)
+            res[path + "_ms_per_100_steps"] = med[105] - med[5]
+        out[name] = dict(workload=f"{side}x{side}, {ns} sheep + {nw} wolves, 100 steps", **res)
+    out["paper_abmax_rm_ms"] = {"small": 50.26, "large": 3315.88}
+    return out
+
+
 def predation_leg(abm, torch, kw, steps, label):
-    """One model on the one-model path (four launches per step): agent updates
+    """One model on the one-model path (three launches per step): agent updates
     per second over `steps` steps (live agents at the start of each step)."""
     model = abm.predation_init(abm.predation_params(**kw))
     stats = torch.zeros((steps, 8), dtype=torch.int64, device="cuda")
@@ -721,6 +762,8 @@ def main():
                                      max_side=args.batched_max_side)
     if "batched_multi_prey" in legs:
         out["batched_multi_prey"] = batched_multi_prey_leg(abm, W, torch)
+    if "table1_context" in legs:
+        out["table1_context"] = table1_context_leg(abm, torch)
     torch.cuda.empty_cache()
     if args.served_seconds > 0:
         out["served"] = served_leg(args.served_seconds, team_size=args.served_team_size)
