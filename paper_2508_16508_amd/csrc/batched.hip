@@ -147,6 +147,19 @@ __device__ __forceinline__ uint32_t block_sum32(uint32_t v, uint32_t* lds) {
     return s;
 }
 
+// Block-wide maximum of one value per thread (every thread gets it); lds
+// holds one word per wave.  Two barriers.
+__device__ __forceinline__ int32_t block_max32(int32_t v, uint32_t* lds) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = uint32_t(v);
+    __syncthreads();
+    int32_t m = int32_t(lds[0]);
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) m = max(m, int32_t(lds[w]));
+    return m;
+}
+
 // Block-wide inclusive scan of one value per thread: *incl gets this thread's
 // inclusive prefix, the return value the block total.  lds holds one word per
 // wave.
@@ -241,6 +254,8 @@ struct Team {
     int32_t* s_pre;             // LDS: breeder prefixes [2][kMaxTeam + 1], free prefix [2], live
     int32_t* s_ok;              // LDS: barrier outcome
     int32_t* s_bound;           // LDS: [2][kMaxTeam + 1] member range bounds of this launch
+    int32_t* s_mark;            // LDS: [2] per species, 1 + the member's highest live slot after
+                                // the last step (no live agent at or above it), or INT32_MAX
 };
 
 __device__ __forceinline__ int32_t* member_list(const Team& tm, int j) {
@@ -370,17 +385,28 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
     }
     const int32_t list1 = v.cap[0];
     int32_t* my_list = member_list(tm, tm.r);
+    // passes A and B visit [lo, eff): every live agent of the range lies below
+    // the mark the last step left.  Each wave copies the mark into registers
+    // here, after the barrier that ended the last step, and the mark is written
+    // again only after every loop of this step (behind the barriers of the
+    // reduction that computes it), so every wave runs the same trip counts.
+    int32_t eff[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int32_t mk = tm.s_mark[s];
+        eff[s] = __builtin_amdgcn_readfirstlane(max(lo[s], min(hi[s], mk)));
+    }
 
     // ---- A: move + claims
     uint32_t live = 0;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
+        for (int32_t c0 = lo[s]; c0 < eff[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < hi[s] ? v.al[s][i] : 0;
+                al[k] = i < eff[s] ? v.al[s][i] : 0;
             }
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
@@ -418,11 +444,11 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
 
     // ---- multi-prey: wolves of this member take their prey
     if (v.multi) {
-        for (int32_t c0 = lo[1]; c0 < hi[1]; c0 += chunk) {
+        for (int32_t c0 = lo[1]; c0 < eff[1]; c0 += chunk) {
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t j = c0 + lbase + k * 64;
-                if (j >= hi[1] || v.al[1][j] == 0) continue;
+                if (j >= eff[1] || v.al[1][j] == 0) continue;
                 const int32_t x = v.x[1][j], y = v.y[1][j];
                 if (!on_grid(v, x, y)) continue;
                 prey_match(v, skey, claims + 3 * (int64_t(y) * v.W + x), j, rd, head);
@@ -432,17 +458,17 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
     }
 
     // ---- B: eat, member-local breeder lists (ascending), free-slot counts
-    uint32_t nb_local[2], nf_local[2];
+    uint32_t nb_local[2], nf_local[2], nf_below[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         uint32_t base_rank = 0, nfree = 0;
         int32_t* list = my_list + (s ? list1 : 0);
-        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
+        for (int32_t c0 = lo[s]; c0 < eff[s]; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < hi[s] ? v.al[s][i] : -1;
+                al[k] = i < eff[s] ? v.al[s][i] : -1;
             }
             bool br[ITEMS];
 #pragma unroll
@@ -487,7 +513,8 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
             base_rank += tot;
         }
         nb_local[s] = base_rank;
-        nf_local[s] = block_sum32(nfree, lds);
+        nf_below[s] = block_sum32(nfree, lds);
+        nf_local[s] = nf_below[s] + uint32_t(hi[s] - eff[s]);   // slots past the mark are free
     }
     // s_pre: [0, K] breeder prefix of species 0, [K+1, 2K+1] of species 1,
     // then the free-slot prefix of this member for both species and the live total
@@ -539,6 +566,7 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
     }
     *live_out = uint32_t(fpre[2]);
 
+    int32_t top[2] = {0, 0};   // 1 + the highest slot this thread leaves alive
     // ---- C: breed into free slots, starve; re-arm the claims (every read of
     // the table in B is behind the barrier above): LOCAL every step, else at
     // the end of a tag period and at the last step of the launch, each team
@@ -556,18 +584,24 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
         const uint32_t nb = uint32_t(bpre[tm.K]);
         const int32_t list_off = s ? list1 : 0;
         uint32_t base_rank = uint32_t(fpre[s]);
-        for (int32_t c0 = lo[s]; c0 < hi[s]; c0 += chunk) {
+        // births into this range: its free slots of model rank below nb; the
+        // ones past the free slots below the mark take [eff, eff + above)
+        const int64_t into = min(max(int64_t(nb) - int64_t(fpre[s]), int64_t(0)),
+                                 int64_t(nf_local[s]));
+        const int32_t above = int32_t(max(into - int64_t(nf_below[s]), int64_t(0)));
+        const int32_t end = __builtin_amdgcn_readfirstlane(min(hi[s], eff[s] + above));
+        for (int32_t c0 = lo[s]; c0 < end; c0 += chunk) {
             int32_t al[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                al[k] = i < hi[s] ? v.al[s][i] : 1;
+                al[k] = i < end ? v.al[s][i] : 1;
             }
             bool fr[ITEMS];
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
                 const int32_t i = c0 + lbase + k * 64;
-                fr[k] = i < hi[s] && (al[k] == 0 || al[k] == 2);
+                fr[k] = i < end && (al[k] == 0 || al[k] == 2);
             }
             uint32_t rank[ITEMS];
             const uint32_t tot = chunk_rank<ITEMS>(fr, rank, lds);
@@ -586,14 +620,25 @@ __device__ bool model_step(const ModelView& v, uint32_t t, uint32_t t0, bool las
                     v.e[s][i] = ec;
                     v.e[s][p] = ep - ec;
                     v.al[s][i] = 1;
-                } else if (i < hi[s]) {
+                    top[s] = i + 1;
+                } else if (i < end) {
                     // a breeder's energy stays positive, so no slot read by a child dies
                     // here, whichever of its two values another member's child leaves
-                    if (al[k] == 2 || (al[k] != 0 && v.e[s][i] < 0)) v.al[s][i] = 0;
+                    if (al[k] == 2 || (al[k] != 0 && v.e[s][i] < 0))
+                        v.al[s][i] = 0;
+                    else if (al[k] != 0)
+                        top[s] = i + 1;
                 }
             }
             base_rank += tot;
         }
+    }
+    // the next step's marks (every wave is past its loops: the reduction's
+    // first barrier comes after them)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int32_t m = block_max32(top[s], lds);
+        if (threadIdx.x == 0) tm.s_mark[s] = m;
     }
     // births, deaths and re-armed claims are visible to the next step
     return team_sync(tm);
@@ -735,10 +780,13 @@ __device__ bool run_model(const BatchArgs& a, int32_t m, Team& tm, uint32_t* lds
     if (tm.K > 1 && t1 > t0 && !balance_team<ITEMS>(v, tm, lds)) return false;
     uint64_t updates = 0;
     const bool local = tm.K == 1 && 3 * int64_t(v.W) * v.H <= a.lds_words;
-    if (local && t1 > t0) {
-        local_fill(local_claims(), 3 * v.W * v.H);
-        __syncthreads();
+    if (local && t1 > t0) local_fill(local_claims(), 3 * v.W * v.H);
+    // no mark yet: the first step of the launch visits the whole range
+    if (threadIdx.x == 0) {
+        tm.s_mark[0] = INT32_MAX;
+        tm.s_mark[1] = INT32_MAX;
     }
+    __syncthreads();
     for (int32_t t = t0; t < t1; ++t) {
         uint32_t live;
         const bool last = t + 1 == t1;
@@ -764,6 +812,7 @@ __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
     __shared__ int32_t s_pre[2 * (kMaxTeam + 1) + 3];
     __shared__ int32_t s_ok, s_model;
     __shared__ int32_t s_bound[2 * (kMaxTeam + 1)];
+    __shared__ int32_t s_mark[2];
     const uint32_t b = blockIdx.x;
     Team tm;
     tm.gen = 0;
@@ -774,6 +823,7 @@ __global__ __launch_bounds__(1024) void k_batched_run(BatchArgs a) {
     tm.s_pre = s_pre;
     tm.s_ok = &s_ok;
     tm.s_bound = s_bound;
+    tm.s_mark = s_mark;
     if (b < a.team_wgs) {
         const uint32_t xcd = b % 8, idx = b / 8;
         const uint32_t team = xcd + 8 * (idx / a.team_k);
