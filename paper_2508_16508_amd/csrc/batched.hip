@@ -7,9 +7,10 @@
 // take models from a queue in a host-chosen order (largest first) until the
 // queue is empty; a model whose work is done is skipped.
 //
-// Per step, three passes over the model's slots in chunks of blockDim x ITEMS:
+// Per step, three passes over the model's slots in chunks of blockDim x ITEMS
+// (below each range's high-water mark, see model_step):
 //   A  move + claims   live agents move, pay one energy and post packed
-//                      (draw << 32 | slot) keys by 64-bit atomicMin into the
+//                      (tag, draw, slot) keys by 64-bit atomicMin into the
 //                      three claim words of their cell (grass, prey, eater);
 //   B  eat + breeders  each live agent compares its keys with the reduced
 //                      words; grass winners gain and set the cell's regrowth
@@ -30,8 +31,7 @@
 // A model run by one workgroup whose claim table (three words per cell) fits
 // in the workgroup's dynamic LDS keeps it there (LOCAL): the table is set to
 // all-ones when the model is taken, pass A posts into it with LDS atomics, and
-// pass C clears it whole instead of re-arming cell by cell (so C reads no
-// positions).  The global table of such a model is not touched.  The launch
+// pass C clears it whole every step.  The global table of such a model is not touched.  The launch
 // gives each workgroup the LDS its occupancy leaves free, so no workgroup
 // is displaced for it.
 // Grass is stored as the step at which a cell is grown again (0 = grown from
