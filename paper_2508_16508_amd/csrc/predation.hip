@@ -63,7 +63,9 @@ constexpr int kHelpers = 2;
 // header words of the free-slot totals (words 4 and 5 are unused by the
 // common layout)
 constexpr int kHdrFreeA = 4, kHdrFreeB = 5;
-static_assert(kHdrFreeA > kHdrCountB && kHdrFreeB < kHdrError, "header word clash");
+// words 6-9: the tile marks of even and odd steps (two species each)
+constexpr int kHdrMark = 6;
+static_assert(kHdrFreeA > kHdrCountB && kHdrMark + 3 < kHdrError, "header word clash");
 static_assert(kWaves * kHelpers >= 2 * kLevels, "the dual-chain prefix needs 2 kLevels waves");      // list entries per thread and batch
 constexpr uint64_t kNoClaim = ~0ull;
 
@@ -115,6 +117,8 @@ struct StepArgs {
     uint32_t chain_off[2];  // start of each species' breeder scan chain in the status words
     uint32_t fchain_off[2]; // ... and of its free-slot scan chain
     int32_t multi;          // prey by rank within a cell (K1 builds lists, K1b matches)
+    uint64_t* mark_rd;      // [2] per species: no live agent in this tile or past it
+    uint64_t* mark_wr;      // [2] the same for the next step, raised by K3 (cleared by K1)
 };
 
 __device__ __forceinline__ int32_t wrap_step(int32_t v, int32_t d, int32_t n) {
@@ -415,6 +419,8 @@ __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
     // other half of the accumulators
     if (a.fold_row && blockIdx.x == gridDim.x - 1)
         fold_stats(a.acc + (kHalfLanes - a.acc_par), a.fold_row);
+    // the next step's tile marks start from zero (K3 raises them)
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x < 2) a.mark_wr[threadIdx.x] = 0;
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     if (!__syncthreads_or(mask != 0u)) return;   // no live agent in the tile
@@ -517,6 +523,20 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
     const int s = t.s;
     const Species sp = a.sp[s];
     const uint32_t epoch = read_epoch(a.epoch);
+    const int64_t cap = s ? a.cap_w : a.cap_s;
+    // tiles at or past the mark hold no live agent: no breeder, every slot
+    // free; they take no part in the scans (no tile below them reads their
+    // words), and K3 derives their free-slot prefixes from the totals
+    const uint32_t mark = uint32_t(a.mark_rd[s]);
+    const uint32_t last = mark > 0 ? mark - 1 : 0;   // the tile that writes the totals
+    const int64_t past = cap - int64_t(mark) * kTile > 0 ? cap - int64_t(mark) * kTile : 0;
+    if (t.tile >= mark) {
+        if (mark == 0 && t.tile == 0 && threadIdx.x == 0) {
+            *a.d_nb[s] = 0;
+            *a.d_nf[s] = cap;
+        }
+        return;
+    }
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     // (a tile with no live agent skips the list: it still takes part in both scans)
@@ -577,7 +597,6 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
     const bool owner = threadIdx.x < kBlock;
     const uint32_t bm = flagged(mask, first, list, 1);
     const uint32_t eaten_m = flagged(mask, first, list, 2);
-    const int64_t cap = s ? a.cap_w : a.cap_s;
     const int64_t lane0 = t.base + int64_t(threadIdx.x) * 32;
     const uint32_t in_cap = !owner || lane0 >= cap ? 0u
                           : (cap - lane0 >= 32 ? ~0u : (1u << (cap - lane0)) - 1u);
@@ -592,9 +611,9 @@ __global__ __launch_bounds__(kBlock * H) void k_eat_breeders(StepArgs a) {
     for (uint32_t m = bm; m; m &= m - 1u)
         a.blist[s][r++] = int32_t(t.base + threadIdx.x * 32u + (__ffs(m) - 1));
     if (threadIdx.x == 0) a.free_pre[s][t.tile] = int32_t(free_excl);
-    if (t.tile == a.tiles[s] - 1 && threadIdx.x == 0) {
+    if (t.tile == last && threadIdx.x == 0) {
         *a.d_nb[s] = int64_t(tile_excl) + total;
-        *a.d_nf[s] = int64_t(free_excl) + total_f;
+        *a.d_nf[s] = int64_t(free_excl) + total_f + past;
     }
     if (a.stats && s == 0) {
         block_add(grass_eaten, a.acc + a.acc_par, kGrassEaten, lds);
@@ -632,7 +651,17 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     }
     // a tile with no live agent and no birth (its free slots rank past the
     // breeders) has nothing to do
-    const bool births_here = int64_t(a.free_pre[s][t.tile]) < nb;
+    // the tile's free-slot prefix: from K2's scan below the mark; past it every
+    // slot of every tile is free
+    const uint32_t mark = uint32_t(a.mark_rd[s]);
+    int64_t pre;
+    if (t.tile < mark) {
+        pre = a.free_pre[s][t.tile];
+    } else {
+        const int64_t past = cap - int64_t(mark) * kTile > 0 ? cap - int64_t(mark) * kTile : 0;
+        pre = (*a.d_nf[s] - past) + int64_t(t.tile - mark) * kTile;
+    }
+    const bool births_here = pre < nb;
     if (!__syncthreads_or(mask != 0u) && !births_here) return;
     uint32_t first;
     const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
@@ -676,7 +705,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
     // (the same free slots K2 ranked: its chain gave this tile's prefix)
     uint32_t r0;
     const uint32_t total = rank_block<kWaves * H>(__popc(free_m), &r0, lds);
-    const uint32_t tile_excl = uint32_t(a.free_pre[s][t.tile]);
+    const uint32_t tile_excl = uint32_t(pre);
     const int64_t room = nb - int64_t(tile_excl);
     const uint32_t births = room <= 0 ? 0u : (room < int64_t(total) ? uint32_t(room) : total);
     // this lane's free slots of tile rank < births receive children
@@ -686,7 +715,12 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
         uint32_t m = free_m;
         for (uint32_t k = 0; k < mine && m; ++k, m &= m - 1u) born_m |= m & (0u - m);
     }
-    if (owner) a.bits[s][wi] = (mask & ~eaten_m & ~starved_m) | born_m;
+    const uint32_t live_m = (mask & ~eaten_m & ~starved_m) | born_m;
+    if (owner) a.bits[s][wi] = live_m;
+    // the next step's mark: past the last tile left with a live agent
+    if (__syncthreads_or(live_m != 0u) && threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(a.mark_wr + s),
+                  (unsigned long long)(t.tile + 1));
     // the children, spread over the block: list the free slots that receive one
     uint32_t bfirst;
     const uint32_t nborn = block_list<kWaves * H>(born_m, list, wl, &bfirst);
@@ -726,6 +760,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
 __global__ __launch_bounds__(kBlock) void k_call_begin(StepArgs a, int64_t G, int64_t words_s,
                                                        int64_t words_w) {
     const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (k < 2) a.mark_rd[k] = a.tiles[k];   // the first step visits every tile
     if (k < G) {
         a.ready[k] = int32_t(a.step + uint32_t(a.ready[k]));
         a.claims[3 * k] = kNoClaim;
@@ -899,6 +934,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
     a.stats = nullptr;
     a.acc_par = 0;
     a.fold_row = nullptr;
+    a.mark_rd = w.hdr + kHdrMark;
+    a.mark_wr = w.hdr + kHdrMark + 2;
     // claim keys (claim_key): slots below 2^sb, a tag of up to kTagBits bits
     // sb + 32 bits up; a period of steps uses the tags t_max - 1 down to 1 (tag
     // 0 every step when only one tag bit is left), and its last step re-arms
@@ -930,6 +967,8 @@ extern "C" int abm_predation_step(const abm_predation_params* p, abm_predation_s
         a.step = s->step + uint32_t(k);
         a.stats = s->stats ? s->stats + 8 * int64_t(k) : nullptr;
         a.acc_par = (k & 1) ? kHalfLanes : 0;
+        a.mark_rd = w.hdr + kHdrMark + 2 * (k & 1);
+        a.mark_wr = w.hdr + kHdrMark + 2 * ((k + 1) & 1);
         a.fold_row = s->stats && k > 0 ? s->stats + 8 * int64_t(k - 1) : nullptr;
         const uint64_t phase = uint64_t(k) % period;
         a.tag_hi = ((t_max > 1 ? t_max - 1 : 0) - phase) << (32 + sb);
