@@ -421,6 +421,7 @@ __global__ __launch_bounds__(kBlock * H) void k_move_claim(StepArgs a) {
         fold_stats(a.acc + (kHalfLanes - a.acc_par), a.fold_row);
     // the next step's tile marks start from zero (K3 raises them)
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x < 2) a.mark_wr[threadIdx.x] = 0;
+    if (t.tile >= uint32_t(a.mark_rd[s])) return;   // past the last live tile
     const uint32_t mask =
         threadIdx.x < kBlock ? a.bits[s][int64_t(t.tile) * kBlock + threadIdx.x] : 0u;
     if (!__syncthreads_or(mask != 0u)) return;   // no live agent in the tile
@@ -662,6 +663,7 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
         pre = (*a.d_nf[s] - past) + int64_t(t.tile - mark) * kTile;
     }
     const bool births_here = pre < nb;
+    if (t.tile >= mark && !births_here) return;   // no live agent, no birth
     if (!__syncthreads_or(mask != 0u) && !births_here) return;
     uint32_t first;
     const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
