@@ -650,8 +650,6 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
         const int64_t nfree = *a.d_nf[s];
         a.stats[s ? kBirthsW : kBirthsS] = nfree < nb ? nfree : nb;
     }
-    // a tile with no live agent and no birth (its free slots rank past the
-    // breeders) has nothing to do
     // the tile's free-slot prefix: from K2's scan below the mark; past it every
     // slot of every tile is free
     const uint32_t mark = uint32_t(a.mark_rd[s]);
@@ -662,8 +660,10 @@ __global__ __launch_bounds__(kBlock * H) void k_breed_die(StepArgs a) {
         const int64_t past = cap - int64_t(mark) * kTile > 0 ? cap - int64_t(mark) * kTile : 0;
         pre = (*a.d_nf[s] - past) + int64_t(t.tile - mark) * kTile;
     }
+    // a tile with no live agent and no birth (its free slots rank past the
+    // breeders) has nothing to do
     const bool births_here = pre < nb;
-    if (t.tile >= mark && !births_here) return;   // no live agent, no birth
+    if (t.tile >= mark && !births_here) return;
     if (!__syncthreads_or(mask != 0u) && !births_here) return;
     uint32_t first;
     const uint32_t n = block_list<kWaves * H>(mask, list, wl, &first);
