@@ -18,17 +18,20 @@
 //   K2 eat+breeders each live agent compares its keys with the reduced table
 //                   entries (grass winner, eaten sheep, eating wolf), applies
 //                   the energy gain and marks an eaten sheep alive = 2, then
-//                   decides whether it breeds; breeders are compacted into an
-//                   ascending list with the single-pass scan (one scan chain
-//                   per species).
-//   K3 breed+die    at the end of a tag period the claim tables are re-armed
-//                   (each workgroup streams its slice; within a period the
-//                   falling tags make older words lose, see claim_key); free slots (alive == 0, or
-//                   eaten this step) are ranked by the same scan, and the free
-//                   slot of rank j <
-//                   #breeders PULLS its child from breeder j (cell, half the
-//                   energy) while the parent keeps the rest; live agents with
-//                   negative energy die.
+//                   decides whether it breeds; the tile's breeders and its
+//                   slots free for births (empty, or eaten this step) are
+//                   ranked by the single-pass scan on two chains at once, the
+//                   breeders compacted into an ascending list and the tile's
+//                   free-slot prefix kept for K3.
+//   K3 breed+die    the free slot of rank j < #breeders PULLS its child from
+//                   breeder j (cell, half the energy) while the parent keeps
+//                   the rest; live agents with negative energy die; at the end
+//                   of a tag period the claim tables are re-armed (each
+//                   workgroup streams its slice; within a period the falling
+//                   tags make older words lose, see claim_key).
+// Tiles past the last tile holding a live agent (the tile mark K3 leaves for
+// the next step) skip their work: they hold no agent, K2's scans stop below
+// them, and K3 computes their free-slot prefixes from the totals.
 // With multi_prey, K1 instead pushes every live sheep and wolf onto a list of
 // its cell (64-bit atomicExch on the prey / eater words, which then hold list
 // heads), and K1b, between K1 and K2, pairs the r-th wolf of each cell (eat
