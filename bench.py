@@ -17,6 +17,7 @@ launch / mean launch time from HIP events on the launch stream) and the CPU
 oracle timed on this host over a bounded sample.
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -658,11 +659,14 @@ def main():
     for s in range(args.warmup):
         step(s, False)
     torch.cuda.synchronize()
-    # the device starts the timed launches only after a short spin, so the
-    # host has queued the first ones by then and the per-launch events measure
-    # the device, not the host's call latency
+    # the device starts the timed launches only after a spin long enough for
+    # the host to queue all of them, so the events time the device and not
+    # the host: a host pause inside a call (a fresh box's first process has
+    # shown 40 ms ones) would otherwise leave the device idle inside that
+    # launch's events; the collector stays off while the calls are made
+    gc.disable()
     if hasattr(torch.cuda, "_sleep"):
-        torch.cuda._sleep(20_000_000)
+        torch.cuda._sleep(250_000_000)
     t0 = time.perf_counter()
     g0 = torch.cuda.Event(enable_timing=True)
     g1 = torch.cuda.Event(enable_timing=True)
@@ -671,6 +675,7 @@ def main():
         step(args.warmup + s, True)
     g1.record(stream)
     torch.cuda.synchronize()
+    gc.enable()
     wall = time.perf_counter() - t0
     ms_total = g0.elapsed_time(g1)
     ms_per_step = ms_total / args.steps
