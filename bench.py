@@ -92,6 +92,16 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+def _queue_ahead(torch):
+    """Before a timed region that the host enqueues call by call: the device
+    spins for about 100 ms, so the host has queued the region's launches by the
+    time it starts and a host pause cannot leave the device idle inside the
+    events; the collector stays off until the region is over (gc.enable)."""
+    gc.disable()
+    if hasattr(torch.cuda, "_sleep"):
+        torch.cuda._sleep(250_000_000)
+
+
 def _med(xs):
     xs = sorted(xs)
     return xs[len(xs) // 2]
@@ -388,10 +398,12 @@ def predation_leg(abm, torch, kw, steps, label):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    _queue_ahead(torch)
     e0.record()
     model.run(steps, stats)
     e1.record()
     torch.cuda.synchronize()
+    gc.enable()
     ms = e0.elapsed_time(e1)
     upd = int(stats[:, 0].sum().item() + stats[:, 1].sum().item())
     err = abm.workspace_error(model.ws)
@@ -664,9 +676,7 @@ def main():
     # the host: a host pause inside a call (a fresh box's first process has
     # shown 40 ms ones) would otherwise leave the device idle inside that
     # launch's events; the collector stays off while the calls are made
-    gc.disable()
-    if hasattr(torch.cuda, "_sleep"):
-        torch.cuda._sleep(250_000_000)
+    _queue_ahead(torch)
     t0 = time.perf_counter()
     g0 = torch.cuda.Event(enable_timing=True)
     g1 = torch.cuda.Event(enable_timing=True)
