@@ -56,20 +56,22 @@ constexpr uint32_t kTagBits = 4;                  // claim-key tag: periods of 1
 #ifndef ABM_PRED_IN_FLIGHT
 #define ABM_PRED_IN_FLIGHT 4
 #endif
-constexpr int kInFlight = ABM_PRED_IN_FLIGHT;
+constexpr int kInFlight = ABM_PRED_IN_FLIGHT;      // list entries per thread and batch
 // Threads per tile: kBlock own the tile's bitmask words, and kHelpers times
 // as many share the tile's list of agents.  Live agents crowd the low tiles
 // (children take the lowest free slots), so a few hundred tiles hold all the
-// work; twice the threads on each measured 9% less time per step at 2048^2
-// (four times: slower, the idle tiles then need more dispatch rounds).
-constexpr int kHelpers = 2;
+// work.  At 2048^2, twice the threads on each took 9% off the step and four
+// times (1024-thread blocks, the most a block holds) a further 8%: the tiles
+// past the last live one exit at once, so the larger blocks cost no extra
+// dispatch rounds.
+constexpr int kHelpers = 4;
 // header words of the free-slot totals (words 4 and 5 are unused by the
 // common layout)
 constexpr int kHdrFreeA = 4, kHdrFreeB = 5;
 // words 6-9: the tile marks of even and odd steps (two species each)
 constexpr int kHdrMark = 6;
 static_assert(kHdrFreeA > kHdrCountB && kHdrMark + 3 < kHdrError, "header word clash");
-static_assert(kWaves * kHelpers >= 2 * kLevels, "the dual-chain prefix needs 2 kLevels waves");      // list entries per thread and batch
+static_assert(kWaves * kHelpers >= 2 * kLevels, "the dual-chain prefix needs 2 kLevels waves");
 constexpr uint64_t kNoClaim = ~0ull;
 
 // Offsets of the eight neighbours, indexed by dir = draw >> 29, packed as
