@@ -53,10 +53,14 @@ constexpr int kWaves = 4;
 constexpr int kBlock = 256;
 constexpr int64_t kTile = int64_t(kBlock) * 32;   // 8192 slots: one bitmask word per thread
 constexpr uint32_t kTagBits = 4;                  // claim-key tag: periods of 14 steps
+// List entries per thread and batch.  With 1024 threads a tile, one each
+// measured 102 us per 2048^2 step against 104 with two and 106 with four:
+// the waves hide the latency of the random cell accesses better than a
+// thread's own batch does.
 #ifndef ABM_PRED_IN_FLIGHT
-#define ABM_PRED_IN_FLIGHT 4
+#define ABM_PRED_IN_FLIGHT 1
 #endif
-constexpr int kInFlight = ABM_PRED_IN_FLIGHT;      // list entries per thread and batch
+constexpr int kInFlight = ABM_PRED_IN_FLIGHT;
 // Threads per tile: kBlock own the tile's bitmask words, and kHelpers times
 // as many share the tile's list of agents.  Live agents crowd the low tiles
 // (children take the lowest free slots), so a few hundred tiles hold all the
