@@ -6,10 +6,10 @@
 // again (grown at step t iff ready <= t), so no per-step regrow pass is needed,
 // and a bitmask in the workspace marks the live slots, so the per-step kernels
 // read 1 bit per slot instead of the 4-byte alive word and visit only live
-// agents.  Each kernel works on tiles of 8192 slots (512 threads, thread t <
+// agents.  Each kernel works on tiles of 8192 slots (1024 threads, thread t <
 // 256 owning the 32 slots of bitmask word t); a tile first compacts its live
 // slots into a list in LDS and then spreads that list over all its threads,
-// four agents per thread in flight, so dense and sparse tiles alike keep every
+// one agent per thread per batch, so dense and sparse tiles alike keep every
 // lane busy.  Step t is three launches (each arrow a grid-wide dependency):
 //   K1 move+claim   every live agent moves, pays 1 energy and posts its
 //                   packed (step tag, draw, slot) key with a 64-bit atomicMin
