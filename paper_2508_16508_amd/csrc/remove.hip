@@ -1,18 +1,20 @@
 // remove.hip -- abm_remove_agents: the paper's set_agents_mask (Sec. 2), an
 // independent masked update with no ranking: alive[i] = 0 wherever kill[i].
 //
-// Each lane owns 32 consecutive slots: two 16-byte loads of the kill mask,
-// then, when one of its kill bytes is set, eight 16-byte loads and stores of
-// alive -- its whole 128-byte line (a sparse kill mask touches only the alive
-// lines it needs).  The line is always stored whole, the unchanged chunks with
-// the values they hold, because HBM3E has no byte mask: a partly written
-// sector costs the memory a read-modify-write, which a later kernel pays for
-// when the partly dirty line leaves the caches.  The conditional
-// accesses are buffer instructions whose offset is moved out of range when not
-// wanted -- the hardware then skips the access -- so there are no branches and
-// all eight loads are in flight together.  Every workgroup but the last
-// publishes its removed count as an epoch-tagged status word; the last one
-// sums them (no same-address atomics, which serialise).
+// A workgroup owns 8192 slots, 256 lines of 32 alive words (128 bytes).  The
+// lanes take 16-byte chunks in order, eight lanes to a line, so one wave
+// instruction covers eight whole lines (and the matching 256 kill bytes).  A
+// line with a kill byte set is loaded whole and, when one of its slots was
+// live, stored whole, the unchanged chunks with the values they hold: HBM3E
+// has no byte mask, so a partly written sector costs the memory a
+// read-modify-write, which a later kernel pays for when the partly dirty line
+// leaves the caches.  Whether the line is wanted is one ballot over its eight
+// lanes.  The conditional accesses are buffer instructions whose offset is
+// moved out of range when not wanted -- the hardware then skips the access --
+// so there are no branches and all of a lane's loads are in flight together.
+// Every workgroup but the last publishes its removed count as an epoch-tagged
+// status word; the last one sums them (no same-address atomics, which
+// serialise).
 #include <hip/hip_runtime.h>
 
 #include "abm.h"
@@ -23,66 +25,57 @@ namespace abm {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSlotsPerLane = 32;
+constexpr int64_t kSlotsPerBlock = 8192;
+constexpr int kPasses = int(kSlotsPerBlock / (4 * kBlock));   // chunks per lane
 constexpr int kSkip = int(0x80000000u);   // out-of-range buffer offset: access skipped
-constexpr int64_t kSlotsPerBlock = int64_t(kBlock) * kSlotsPerLane;
-// 16-byte chunks per stored group: the lane's whole 128-byte line
-#ifndef ABM_REMOVE_GROUP_CHUNKS
-#define ABM_REMOVE_GROUP_CHUNKS 8
-#endif
-constexpr int kGroupChunks = ABM_REMOVE_GROUP_CHUNKS;
-static_assert(kGroupChunks == 1 || kGroupChunks == 2 || kGroupChunks == 4 || kGroupChunks == 8,
-              "group of 1, 2, 4 or 8 chunks");
-
-// Bits of the lane's eight chunks that share chunk q's group.
-__device__ __forceinline__ constexpr uint32_t group_of(int q) {
-    return ((1u << kGroupChunks) - 1u) << (q & ~(kGroupChunks - 1));
-}
+constexpr int kRsrcWord3 = 0x00020000;    // raw buffer descriptor, 32-bit data format
 
 __global__ __launch_bounds__(kBlock) void k_remove(const uint8_t* __restrict__ kill,
                                                    int32_t* __restrict__ alive, int64_t n,
                                                    uint64_t* status, EpochArg ep,
                                                    int64_t* d_removed) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
     __shared__ uint32_t lds[kBlock / 64];
     const uint32_t epoch = read_epoch(ep);
-    const int64_t first = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kSlotsPerLane;
+    const int64_t bfirst = int64_t(blockIdx.x) * kSlotsPerBlock;
     uint32_t removed = 0;
-    if (first + kSlotsPerLane <= n) {
-        typedef int v4i __attribute__((ext_vector_type(4)));
-        const int64_t bfirst = int64_t(blockIdx.x) * kSlotsPerBlock;
-        const int64_t bn = (n - bfirst) < kSlotsPerBlock ? (n - bfirst) : kSlotsPerBlock;
-        const __amdgpu_buffer_rsrc_t ra =
-            __builtin_amdgcn_make_buffer_rsrc(alive + bfirst, 0, int(bn * 4), 0x00020000);
-        const uint4* kp = reinterpret_cast<const uint4*>(kill + first);
-        const uint4 k0 = kp[0], k1 = kp[1];
-        const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
-        const int lo = int(threadIdx.x) * kSlotsPerLane * 4;
-        uint32_t killc = 0;
+    if (bfirst + kSlotsPerBlock <= n) {
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            alive + bfirst, 0, int(kSlotsPerBlock * 4), kRsrcWord3);
+        const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t*>(kill) + bfirst, 0, int(kSlotsPerBlock), kRsrcWord3);
+        // lane l of a wave shares its line with lanes (l & ~7) .. (l | 7)
+        const int first = int(threadIdx.x & 63u) & ~7;
+        uint32_t kw[kPasses];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) killc |= uint32_t(kw[q] != 0u) << q;
-        v4i al[8];
+        for (int p = 0; p < kPasses; ++p)
+            kw[p] = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(
+                rk, (p * kBlock + int(threadIdx.x)) * 4, 0, 0));
+        v4i al[kPasses];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            al[q] = __builtin_amdgcn_raw_buffer_load_b128(
-                ra, (killc & group_of(q)) ? lo + 16 * q : kSkip, 0, 0);
-        uint32_t changed = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (((kw[q] >> (8 * b)) & 0xFFu) != 0u && al[q][b] != 0) {
-                    ++removed;
-                    al[q][b] = 0;
-                    changed |= 1u << q;
-                }
-            }
+        for (int p = 0; p < kPasses; ++p) {
+            const bool line = ((__ballot(kw[p] != 0u) >> first) & 0xFFu) != 0u;
+            al[p] = __builtin_amdgcn_raw_buffer_load_b128(
+                ra, line ? (p * kBlock + int(threadIdx.x)) * 16 : kSkip, 0, 0);
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            __builtin_amdgcn_raw_buffer_store_b128(al[q], ra,
-                                                   (changed & group_of(q)) ? lo + 16 * q : kSkip, 0, 0);
+        for (int p = 0; p < kPasses; ++p) {
+            bool changed = false;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (((kw[p] >> (8 * b)) & 0xFFu) != 0u && al[p][b] != 0) {
+                    ++removed;
+                    al[p][b] = 0;
+                    changed = true;
+                }
+            }
+            const bool line = ((__ballot(changed) >> first) & 0xFFu) != 0u;
+            __builtin_amdgcn_raw_buffer_store_b128(
+                al[p], ra, line ? (p * kBlock + int(threadIdx.x)) * 16 : kSkip, 0, 0);
+        }
     } else {
-        for (int64_t s = first; s < n && s < first + kSlotsPerLane; ++s) {
+        // the partial last workgroup: slot by slot
+        for (int64_t s = bfirst + threadIdx.x; s < n; s += kBlock) {
             if (kill[s] != 0 && alive[s] != 0) {
                 ++removed;
                 alive[s] = 0;
